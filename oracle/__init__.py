@@ -1,0 +1,178 @@
+"""Plain FP64 CPU oracle for the batched polynomial-root path.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.  It shares
+no code with the HIP path.
+
+The arithmetic lives in ``oracle.c`` (plain C99 complex doubles, dense
+storage, -O2 -ffp-contract=off).  This module compiles it with gcc on first
+use when the shared library is missing, and wraps it for numpy arrays.
+
+What each function follows in arXiv 2507.02164:
+  solve     -- Sec. II-B (companion matrix, Alg. 1 single-shift QR iteration)
+               and Sec. II-C (Givens equation, two-row then two-column
+               in-place update, the loop shape of Alg. 2), with a
+               convergence test and exceptional shift where the paper has a
+               fixed iteration count (``fixed_t`` reproduces Alg. 2).
+  density   -- Sec. III, roots converted to pixel coordinates and counted.
+  backward  -- not in the paper: the implicit-function derivative
+               dr/da_k = -r^k / p'(r) of a simple root.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+ST_BAD_DEGREE = 0x1
+ST_NONFINITE = 0x2
+ST_ZERO_LEADING = 0x4
+ST_NOT_CONVERGED = 0x8
+ST_SINGULAR_DERIV = 0x20
+
+FLAG_NO_EXCEPTIONAL_SHIFT = 0x1
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain IEEE doubles)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.oracle_solve.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, P, ctypes.c_int,
+                                     ctypes.c_uint, ctypes.c_int, ctypes.c_int]
+        lib.oracle_solve.restype = None
+        lib.oracle_density.argtypes = [P, P, P, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, P]
+        lib.oracle_density.restype = None
+        lib.oracle_backward.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int]
+        lib.oracle_backward.restype = None
+        lib.oracle_givens.argtypes = [P, P, P, P]
+        lib.oracle_givens.restype = None
+        lib.oracle_qr_step.argtypes = [ctypes.c_int, P, P]
+        lib.oracle_qr_step.restype = None
+        lib.oracle_max_threads.argtypes = []
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _c128(x, shape=None):
+    a = np.ascontiguousarray(x, dtype=np.complex128)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _degrees(degrees, n):
+    if degrees is None:
+        return None
+    d = np.ascontiguousarray(degrees, dtype=np.int32)
+    if d.shape != (n,):
+        raise ValueError("degrees must have shape (n,)")
+    return d
+
+
+def max_threads() -> int:
+    return _load().oracle_max_threads()
+
+
+def solve(coeffs, degrees=None, *, cap: int = 30, flags: int = 0, fixed_t: int = 0,
+          nthreads: int = 0, return_iters: bool = False):
+    """Roots of each column of ``coeffs`` ([dmax+1, n] complex, row k = a_k).
+
+    Returns ``(roots [dmax, n] complex128 in deflation order, NaN beyond the
+    degree; status [n] uint32)`` and, with ``return_iters``, the QR steps per
+    level ``[dmax-1, n]`` (row m-2 = level m)."""
+    coeffs = _c128(coeffs)
+    if coeffs.ndim != 2 or not (2 <= coeffs.shape[0] <= 7):
+        raise ValueError("coeffs must be [dmax+1, n] with 1 <= dmax <= 6")
+    dmax = coeffs.shape[0] - 1
+    n = coeffs.shape[1]
+    deg = _degrees(degrees, n)
+    roots = np.empty((dmax, n), dtype=np.complex128)
+    status = np.zeros(n, dtype=np.uint32)
+    iters = np.zeros((max(dmax - 1, 0), n), dtype=np.int32)
+    _load().oracle_solve(_ptr(coeffs), _ptr(deg), n, dmax, _ptr(roots), _ptr(status),
+                         _ptr(iters) if dmax > 1 else None, cap, flags, fixed_t, nthreads)
+    if return_iters:
+        return roots, status, iters
+    return roots, status
+
+
+def density(roots, window, shape, degrees=None, status=None, skip_mask: int = 0, out=None):
+    """Count roots per pixel.  ``window`` = (x0, x1, y0, y1), half-open;
+    ``shape`` = (width, height); result int32 [height, width], row 0 = lowest
+    imaginary part.  Counts are added to ``out`` when given."""
+    roots = _c128(roots)
+    dmax, n = roots.shape
+    x0, x1, y0, y1 = (float(v) for v in window)
+    width, height = (int(v) for v in shape)
+    if out is None:
+        out = np.zeros((height, width), dtype=np.int32)
+    assert out.dtype == np.int32 and out.shape == (height, width) and out.flags.c_contiguous
+    deg = _degrees(degrees, n)
+    st = None if status is None else np.ascontiguousarray(status, dtype=np.uint32)
+    _load().oracle_density(_ptr(roots), _ptr(deg), _ptr(st), skip_mask, n, dmax,
+                           x0, x1, y0, y1, width, height, _ptr(out))
+    return out
+
+
+def backward(coeffs, roots, grad_roots, degrees=None, status=None, nthreads: int = 0):
+    """Cotangent of the coefficients given root cotangents (PyTorch's
+    convention dL/dRe + i dL/dIm).  Returns ``(grad_coeffs [dmax+1, n],
+    status)`` with SINGULAR_DERIV or-ed in."""
+    coeffs = _c128(coeffs)
+    dmax = coeffs.shape[0] - 1
+    n = coeffs.shape[1]
+    roots = _c128(roots, (dmax, n))
+    grad_roots = _c128(grad_roots, (dmax, n))
+    deg = _degrees(degrees, n)
+    st = np.zeros(n, dtype=np.uint32) if status is None else np.array(status, dtype=np.uint32, copy=True)
+    grad = np.empty((dmax + 1, n), dtype=np.complex128)
+    _load().oracle_backward(_ptr(coeffs), _ptr(deg), _ptr(roots), _ptr(grad_roots), n, dmax,
+                            _ptr(grad), _ptr(st), nthreads)
+    return grad, st
+
+
+def givens(a: complex, b: complex):
+    """(c, s) of the Sec. II-C rotation for the pair (a, b)."""
+    A = np.array([a.real, a.imag]); B = np.array([b.real, b.imag])
+    C = np.zeros(2); S = np.zeros(2)
+    _load().oracle_givens(_ptr(A), _ptr(B), _ptr(C), _ptr(S))
+    return complex(C[0], C[1]), complex(S[0], S[1])
+
+
+def qr_step(H, shift: complex):
+    """One shifted QR step (Alg. 1 body via Sec. II-C rotations) on a dense
+    square complex matrix; returns the new matrix."""
+    H = np.array(H, dtype=np.complex128, copy=True, order="C")
+    m = H.shape[0]
+    assert H.shape == (m, m) and 1 <= m <= 6
+    s = np.array([shift.real, shift.imag])
+    _load().oracle_qr_step(m, _ptr(H), _ptr(s))
+    return H

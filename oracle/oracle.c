@@ -1,0 +1,369 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU reference for the batched polynomial
+ * root path of "Hardware-Accelerated Algorithm for Complex Function Roots
+ * Density Graph Plotting" (Tang & Quan, arXiv 2507.02164).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file's library.  It shares no
+ * code, header, table or helper with the HIP library, and includes none of
+ * its files.
+ *
+ * What it computes:
+ *   oracle_solve     -- roots of p(z) = sum_k a_k z^k as eigenvalues of the
+ *                       Frobenius companion matrix (Sec. II-B), by
+ *                       single-shift QR iteration (Alg. 1) whose QR step is
+ *                       realised with complex Givens rotations applied to two
+ *                       rows, then two columns, in place (Sec. II-C, the loop
+ *                       structure of Alg. 2), with bottom deflation.
+ *   oracle_density   -- roots -> integer pixel counts over a complex window
+ *                       (Sec. III, the roots-to-pixels stage).
+ *   oracle_backward  -- implicit-function adjoint dr/da_k = -r^k / p'(r).
+ *                       The paper has no gradient; this is the textbook
+ *                       derivative of a simple root, written out.
+ *
+ * Storage is a dense row-major d x d matrix and every loop runs over the
+ * dense range Alg. 2 gives (j = 0..m-1); there is no band trimming, fusion
+ * or reordering.  Floating point: compiled with -O2 -ffp-contract=off, so
+ * every complex operation is a sequence of correctly rounded IEEE double
+ * operations (gcc's C99 complex multiply/divide).
+ *
+ * Readings of the paper taken here (where it is silent):
+ *   - companion form: first row -b_{d-1} ... -b_0, ones on the subdiagonal
+ *     (the paper names the Frobenius companion matrix without printing it);
+ *   - Givens pair: the unique (c, s) = (conj(a), conj(b)) / rho that makes
+ *     the Sec. II-C rotation map (a, b) to (rho, 0) with rho = sqrt(|a|^2 +
+ *     |b|^2) >= 0; identity when rho == 0;
+ *   - the annihilated entry is stored as an exact zero after each row
+ *     rotation (the Appendix proves it is zero in exact arithmetic);
+ *   - convergence: instead of Alg. 1's fixed iteration count, a level
+ *     deflates once cabs1(h[m-1][m-2]) <= eps * (cabs1(h[m-1][m-1]) +
+ *     cabs1(h[m-2][m-2])), cabs1(z) = |Re z| + |Im z|, eps = 2^-52;
+ *   - exceptional shift at the 10th and 20th iteration of a level:
+ *     s += cabs1(h[m-1][m-2]) * (0.75 + 0.5i); cap of 30 iterations per
+ *     level, after which the level deflates anyway and NOT_CONVERGED is set;
+ *   - a fixed-T mode (flag) reproduces Alg. 2 literally: exactly T QR steps
+ *     per level, no test, no exceptional shift.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+#include <float.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Status bits (values fixed by the library's public contract; restated here
+ * so that this file depends on nothing but libc). */
+#define OST_BAD_DEGREE 0x1u
+#define OST_NONFINITE 0x2u
+#define OST_ZERO_LEADING 0x4u
+#define OST_NOT_CONVERGED 0x8u
+#define OST_SINGULAR_DERIV 0x20u
+
+/* flags for oracle_solve */
+#define OFLAG_NO_EXCEPTIONAL_SHIFT 0x1u
+#define OFLAG_FIXED_T 0x2u
+
+#define ODMAX 6
+
+typedef double complex cplx;
+
+static double cabs1(cplx z) { return fabs(creal(z)) + fabs(cimag(z)); }
+
+static int cfinite(cplx z) { return isfinite(creal(z)) && isfinite(cimag(z)); }
+
+/* Sec. II-C equation: the unitary [[c, s], [-conj(s), conj(c)]] maps
+ * (a, b) to (sqrt(|a|^2 + |b|^2), 0).  The only such pair is
+ * c = conj(a)/rho, s = conj(b)/rho (Cauchy-Schwarz equality).  rho == 0
+ * leaves the rows unchanged (identity rotation). */
+void oracle_givens(const double *a_ri, const double *b_ri, double *c_ri, double *s_ri)
+{
+    cplx a = a_ri[0] + I * a_ri[1];
+    cplx b = b_ri[0] + I * b_ri[1];
+    double rho = hypot(cabs(a), cabs(b));
+    cplx c = 1.0, s = 0.0;
+    if (rho != 0.0) {
+        c = conj(a) / rho;
+        s = conj(b) / rho;
+    }
+    c_ri[0] = creal(c);
+    c_ri[1] = cimag(c);
+    s_ri[0] = creal(s);
+    s_ri[1] = cimag(s);
+}
+
+/* One shifted QR step on the leading m x m block of the dense matrix H
+ * (row-major, leading dimension ld), Alg. 1 body: A <- A - sI; A = QR;
+ * A <- RQ + sI.  The QR factorisation is never formed: as Sec. II-C and
+ * Alg. 2 describe, the rotations Q_1..Q_{m-1} are applied to two rows at a
+ * time (A <- Q_{m-1}..Q_1 A), then their conjugate transposes to two
+ * columns at a time (A <- A Q_1^H .. Q_{m-1}^H). */
+static void qr_step(int m, int ld, cplx *H, cplx shift)
+{
+    cplx c[ODMAX], sn[ODMAX];
+#define E(i, j) H[(i) * ld + (j)]
+    for (int i = 0; i < m; ++i)
+        E(i, i) -= shift;
+    /* row pass */
+    for (int r = 1; r < m; ++r) {
+        double a[2] = {creal(E(r - 1, r - 1)), cimag(E(r - 1, r - 1))};
+        double b[2] = {creal(E(r, r - 1)), cimag(E(r, r - 1))};
+        double cc[2], ss[2];
+        oracle_givens(a, b, cc, ss);
+        c[r] = cc[0] + I * cc[1];
+        sn[r] = ss[0] + I * ss[1];
+        for (int j = 0; j < m; ++j) {
+            cplx x = E(r - 1, j), y = E(r, j);
+            E(r - 1, j) = c[r] * x + sn[r] * y;
+            E(r, j) = -conj(sn[r]) * x + conj(c[r]) * y;
+        }
+        E(r, r - 1) = 0.0; /* exact zero: the entry the rotation annihilates */
+    }
+    /* column pass */
+    for (int r = 1; r < m; ++r) {
+        for (int j = 0; j < m; ++j) {
+            cplx x = E(j, r - 1), y = E(j, r);
+            E(j, r - 1) = conj(c[r]) * x + conj(sn[r]) * y;
+            E(j, r) = -sn[r] * x + c[r] * y;
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        E(i, i) += shift;
+#undef E
+}
+
+/* Exposed for tests: one QR step with an explicit shift on a dense m x m
+ * matrix stored as interleaved (re, im) doubles, row-major. */
+void oracle_qr_step(int m, double *H_ri, const double *shift_ri)
+{
+    cplx H[ODMAX * ODMAX];
+    for (int k = 0; k < m * m; ++k)
+        H[k] = H_ri[2 * k] + I * H_ri[2 * k + 1];
+    qr_step(m, m, H, shift_ri[0] + I * shift_ri[1]);
+    for (int k = 0; k < m * m; ++k) {
+        H_ri[2 * k] = creal(H[k]);
+        H_ri[2 * k + 1] = cimag(H[k]);
+    }
+}
+
+/* Roots of one polynomial of degree d with coefficients a[0..d] (a[d]
+ * leading).  eig[0..d-1] receives the eigenvalues in deflation order
+ * (eig[d-1] is found first, eig[0] last, as in Alg. 1).  its[m-2] receives
+ * the number of QR steps taken at level m (m = 2..d).  Returns status bits.
+ */
+static unsigned solve_one(int d, const cplx *a, cplx *eig, int *its_out,
+                          int cap, unsigned flags, int fixed_t)
+{
+    unsigned st = 0;
+    for (int k = 0; k <= d; ++k)
+        if (!cfinite(a[k]))
+            st |= OST_NONFINITE;
+    if (!st && a[d] == 0.0)
+        st |= OST_ZERO_LEADING;
+    if (st) {
+        for (int k = 0; k < d; ++k)
+            eig[k] = NAN + I * NAN;
+        return st;
+    }
+
+    /* Sec. II-B: the roots of p are those of the monic p / a_d. */
+    cplx b[ODMAX + 1];
+    for (int k = 0; k < d; ++k)
+        b[k] = a[k] / a[d];
+    b[d] = 1.0;
+
+    if (d == 1) {
+        eig[0] = -b[0];
+        return st;
+    }
+
+    /* Frobenius companion matrix, first-row form: its characteristic
+     * polynomial is z^d + b_{d-1} z^{d-1} + ... + b_0. */
+    cplx H[ODMAX * ODMAX];
+    for (int k = 0; k < d * d; ++k)
+        H[k] = 0.0;
+    for (int j = 0; j < d; ++j)
+        H[0 * d + j] = -b[d - 1 - j];
+    for (int i = 0; i + 1 < d; ++i)
+        H[(i + 1) * d + i] = 1.0;
+
+    const double eps = DBL_EPSILON; /* 2^-52 */
+    for (int m = d; m >= 2; --m) {
+        int its = 0;
+        for (;;) {
+            cplx hsub = H[(m - 1) * d + (m - 2)];
+            if (fixed_t > 0) {
+                if (its == fixed_t)
+                    break;
+            } else {
+                double h = cabs1(hsub);
+                double t = cabs1(H[(m - 1) * d + (m - 1)]) + cabs1(H[(m - 2) * d + (m - 2)]);
+                if (h <= eps * t)
+                    break;
+                if (its == cap) {
+                    st |= OST_NOT_CONVERGED;
+                    break;
+                }
+            }
+            /* Alg. 1: the shift is the current bottom-right entry. */
+            cplx s = H[(m - 1) * d + (m - 1)];
+            if (fixed_t <= 0 && !(flags & OFLAG_NO_EXCEPTIONAL_SHIFT) && (its == 10 || its == 20))
+                s += cabs1(hsub) * (0.75 + 0.5 * I);
+            qr_step(m, d, H, s);
+            ++its;
+        }
+        if (its_out)
+            its_out[m - 2] = its;
+        /* Alg. 1: record eig[m-1], then continue on the leading block. */
+        eig[m - 1] = H[(m - 1) * d + (m - 1)];
+    }
+    eig[0] = H[0];
+    return st;
+}
+
+/* Batched solve.
+ *   coeffs  [dmax+1][n] complex128 (interleaved re, im), row k = a_k
+ *   degrees [n] int32, or NULL meaning every polynomial has degree dmax
+ *   roots   [dmax][n] complex128 out; NaN for rows k >= d_i
+ *   status  [n] uint32 out
+ *   iters   [dmax-1][n] int32 out or NULL; row m-2 = QR steps at level m
+ *   cap     iterations per level before NOT_CONVERGED (<= 0: 30)
+ *   fixed_t > 0: Alg. 2 literally, exactly fixed_t steps per level
+ *   nthreads <= 0: OpenMP default
+ */
+void oracle_solve(const double *coeffs, const int32_t *degrees, int64_t n, int dmax,
+                  double *roots, uint32_t *status, int32_t *iters, int cap,
+                  unsigned flags, int fixed_t, int nthreads)
+{
+    if (cap <= 0)
+        cap = 30;
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int d = degrees ? degrees[i] : dmax;
+        cplx a[ODMAX + 1], eig[ODMAX];
+        int its[ODMAX];
+        for (int k = 0; k < ODMAX; ++k) {
+            eig[k] = NAN + I * NAN;
+            its[k] = 0;
+        }
+        unsigned st;
+        if (d < 1 || d > dmax) {
+            st = OST_BAD_DEGREE;
+        } else {
+            for (int k = 0; k <= d; ++k)
+                a[k] = coeffs[2 * (k * n + i)] + I * coeffs[2 * (k * n + i) + 1];
+            st = solve_one(d, a, eig, its, cap, flags, fixed_t);
+        }
+        for (int k = 0; k < dmax; ++k) {
+            cplx r = (k < d && d <= dmax) ? eig[k] : NAN + I * NAN;
+            roots[2 * (k * n + i)] = creal(r);
+            roots[2 * (k * n + i) + 1] = cimag(r);
+        }
+        if (iters)
+            for (int k = 0; k < dmax - 1; ++k)
+                iters[k * n + i] = its[k];
+        status[i] = st;
+    }
+}
+
+/* Roots-to-pixels (Sec. III): window [x0, x1) x [y0, y1) split into
+ * width x height pixels, row 0 = lowest imaginary part.  For each root
+ * u = (re - x0) * sx, v = (im - y0) * sy with sx = width / (x1 - x0) and
+ * sy = height / (y1 - y0); the root counts iff 0 <= u < width and
+ * 0 <= v < height (a NaN fails every comparison), in pixel
+ * (floor(v), floor(u)).  Counts are added to hist (the caller zeroes it).
+ * Polynomials with (status & skip_mask) != 0 are skipped; only rows
+ * k < degree are read. */
+void oracle_density(const double *roots, const int32_t *degrees, const uint32_t *status,
+                    uint32_t skip_mask, int64_t n, int dmax, double x0, double x1,
+                    double y0, double y1, int width, int height, int32_t *hist)
+{
+    double sx = (double)width / (x1 - x0);
+    double sy = (double)height / (y1 - y0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (status && (status[i] & skip_mask))
+            continue;
+        int d = degrees ? degrees[i] : dmax;
+        if (d > dmax)
+            d = dmax;
+        for (int k = 0; k < d; ++k) {
+            double re = roots[2 * (k * n + i)];
+            double im = roots[2 * (k * n + i) + 1];
+            double u = (re - x0) * sx;
+            double v = (im - y0) * sy;
+            if (u >= 0.0 && u < (double)width && v >= 0.0 && v < (double)height) {
+                int iu = (int)u, iv = (int)v;
+                hist[(int64_t)iv * width + iu] += 1;
+            }
+        }
+    }
+}
+
+/* Implicit-function adjoint.  At a simple root r of p(z) = sum_k a_k z^k,
+ * p(r(a); a) = 0 gives dr/da_k = -r^k / p'(r).  For a real loss L with
+ * cotangent g_r = dL/dRe r + i dL/dIm r, the cotangent of a_k (same
+ * convention) is conj(dr/da_k) * g_r, summed over the roots.
+ *   grad_coeffs [dmax+1][n] out, zero for rows k > d_i
+ *   status [n] in/out: polynomials with BAD_DEGREE, NONFINITE or
+ *   ZERO_LEADING get zero gradient; a root with p'(r) zero or non-finite
+ *   contributes nothing and sets SINGULAR_DERIV. */
+void oracle_backward(const double *coeffs, const int32_t *degrees, const double *roots,
+                     const double *grad_roots, int64_t n, int dmax, double *grad_coeffs,
+                     uint32_t *status, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int d = degrees ? degrees[i] : dmax;
+        cplx g[ODMAX + 1];
+        for (int k = 0; k <= ODMAX; ++k)
+            g[k] = 0.0;
+        unsigned st = status[i];
+        if (d >= 1 && d <= dmax && !(st & (OST_BAD_DEGREE | OST_NONFINITE | OST_ZERO_LEADING))) {
+            cplx a[ODMAX + 1];
+            for (int k = 0; k <= d; ++k)
+                a[k] = coeffs[2 * (k * n + i)] + I * coeffs[2 * (k * n + i) + 1];
+            for (int j = 0; j < d; ++j) {
+                cplx r = roots[2 * (j * n + i)] + I * roots[2 * (j * n + i) + 1];
+                cplx gr = grad_roots[2 * (j * n + i)] + I * grad_roots[2 * (j * n + i) + 1];
+                /* p'(r) = sum_{k>=1} k a_k r^{k-1}, by Horner */
+                cplx dp = d * a[d];
+                for (int k = d - 1; k >= 1; --k)
+                    dp = dp * r + k * a[k];
+                if (!cfinite(dp) || dp == 0.0) {
+                    st |= OST_SINGULAR_DERIV;
+                    continue;
+                }
+                cplx rk = 1.0;
+                for (int k = 0; k <= d; ++k) {
+                    cplx drda = -rk / dp;
+                    g[k] += conj(drda) * gr;
+                    rk *= r;
+                }
+            }
+        }
+        for (int k = 0; k <= dmax; ++k) {
+            grad_coeffs[2 * (k * n + i)] = creal(g[k]);
+            grad_coeffs[2 * (k * n + i) + 1] = cimag(g[k]);
+        }
+        status[i] = st;
+    }
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
