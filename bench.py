@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark: degree-6 complex polynomials solved per second on one MI355X,
+FP32 sweeps + FP64 Newton polish beside plain FP64.
+
+Workload (default): the 4096 x 4096 parametric grid of monic degree-6
+polynomials a_k = c_k + t1 d_k + t2 e_k (16,777,216 polynomials), binned
+into a 1920 x 1080 root-density image.  One step = the whole path over the
+batch: pr_solve -> pr_density (into a zeroed image) -> pr_backward (seeded
+root cotangents).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is whole-step throughput of the FP32 + polish
+form; the FP64 form is measured the same way and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Per-QR-step FLOPs at level m (band-trimmed complex Givens sweep: 28 per
+# two-entry rotation pair over m(m+1)-2 pairs, 11 per Givens pair, 4m for
+# the shift), and polish FLOPs per root per Newton step at degree d.
+F_LEVEL = {2: 131, 3: 314, 4: 553, 5: 848, 6: 1199}
+PEAK_FP64 = 78.6e12          # MI355X vector FP64, FLOP/s
+PEAK_FP32 = 157.3e12         # MI355X vector FP32 (published; needs packed FP32)
+PEAK_FP32_NONPACKED = 78.6e12
+PEAK_HBM = 8.0e12            # B/s
+
+
+def polish_flops(d, steps):
+    return d * steps * (16 * d + 13)
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def algorithmic_flops(iters):
+    """Sum over polynomials and levels of steps x F(m).  iters [5, n] int."""
+    it = iters.astype(np.float64)
+    return float(sum(it[m - 2].sum() * F_LEVEL[m] for m in range(2, 7)))
+
+
+def cpu_baseline(coeffs_host, target_s=10.0):
+    import oracle
+    threads = oracle.max_threads()
+    n_total = coeffs_host.shape[1]
+    probe = min(65536, n_total)
+    t0 = time.perf_counter()
+    oracle.solve(coeffs_host[:, :probe])
+    dt = time.perf_counter() - t0
+    rate = probe / max(dt, 1e-9)
+    n = int(min(n_total, max(probe, rate * target_s)))
+    sample = np.ascontiguousarray(coeffs_host[:, :n])
+    t0 = time.perf_counter()
+    roots, st = oracle.solve(sample)
+    dt = time.perf_counter() - t0
+    return {
+        "value": n / dt, "unit": "polys/s", "cores": threads, "kind": "oracle",
+        "sample": f"first {n} polynomials of the same grid (rows 0..{(n - 1) // 4096} of 4096), "
+                  f"FP64 oracle solve only, {dt:.1f} s",
+        "host_cpu": platform.processor() or platform.machine(),
+    }, roots, n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=4096, help="grid side; n = grid^2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", choices=["fp32_polish", "fp64"], default=None,
+                    help="run only the timed steps of one form (for profilers)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   f"--gpus {args.gpus} is not supported (polynomials shard "
+                                   "trivially; see DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_2507_02164_amd as pr
+
+    dev = torch.device("cuda:0")
+    g = args.grid
+    n = g * g
+    log(f"generating parametric grid {g}x{g} ({n} polynomials)")
+    a_host = workloads.parametric(g, seed=0)
+    cot_host = workloads.cotangents(n, seed=1)
+    a = torch.from_numpy(a_host).to(dev)
+    cot = torch.from_numpy(cot_host).to(dev)
+    roots = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    status = torch.empty((n,), dtype=torch.int32, device=dev)
+    gcoef = torch.empty_like(a)
+    win, shape = workloads.PARAMETRIC_WINDOW, (1920, 1080)
+    hist = torch.zeros((shape[1], shape[0]), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    forms = ["fp32_polish", "fp64"] if args.profile_only is None else [args.profile_only]
+    res = {}
+    for form in forms:
+        # untimed diagnostic pass: per-level step counts for the FLOP model
+        log(f"{form}: diagnostic pass")
+        _, st_d, its = pr.solve(a, None, form, iter_counts=True, roots=roots, status=status)
+        torch.cuda.synchronize()
+        its_h = its.cpu().numpy()
+        st_h = status.cpu().numpy()
+        flops = algorithmic_flops(its_h)
+        if form == "fp32_polish":
+            flops += n * polish_flops(6, 2)
+        del its
+        stream = torch.cuda.current_stream()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)]
+              for _ in range(args.steps)]
+
+        def step(e=None):
+            if e: e[0].record(stream)
+            pr.solve(a, None, form, roots=roots, status=status)
+            if e: e[1].record(stream)
+            hist.zero_()
+            pr.density(roots, win, shape, status=status, out=hist)
+            if e: e[2].record(stream)
+            pr.backward(a, roots, cot, None, status, grad_coeffs=gcoef)
+            if e: e[3].record(stream)
+
+        log(f"{form}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        log(f"{form}: timing {args.steps} steps")
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(ev[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        solve_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        dens_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        back_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
+        step_ms = wall * 1e3 / args.steps
+        res[form] = dict(step_ms=step_ms, solve_ms=solve_ms, density_ms=dens_ms,
+                         backward_ms=back_ms, polys_per_s=n / (step_ms * 1e-3),
+                         solve_polys_per_s=n / (solve_ms * 1e-3),
+                         alg_flops_per_poly=flops / n,
+                         mean_qr_steps=float(its_h.sum(axis=0).mean()),
+                         flagged_frac=float((st_h != 0).mean()),
+                         alg_tflops=flops / (solve_ms * 1e-3) / 1e12)
+        log(f"{form}: step {step_ms:.3f} ms, solve {solve_ms:.3f} ms, density {dens_ms:.3f} ms, "
+            f"backward {back_ms:.3f} ms")
+
+    main_form = forms[0]
+    r = res[main_form]
+    peak = PEAK_FP32 if main_form == "fp32_polish" else PEAK_FP64
+    achieved = r["alg_tflops"] * 1e12
+    out = {
+        "metric": "deg-6 complex polys solved/s: FP32+FP64-polish vs plain FP64, root err <=1e-10",
+        "value": r["polys_per_s"],
+        "unit": "polys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["step_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if main_form == "fp32_polish" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"parametric grid {g}x{g}: {n} monic degree-6 complex polynomials "
+                               "a_k = c_k + t1 d_k + t2 e_k, 1920x1080 int32 density image, "
+                               "step = solve + density + backward",
+                   "n_polys": n, "degree": 6, "image": [1920, 1080], "form": main_form},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": f"solve_{main_form}",
+                     "flops_per_launch": r["alg_flops_per_poly"] * n,
+                     "avg_launch_ms": r["solve_ms"]},
+        "forms": res,
+    }
+    if "fp64" in res and "fp32_polish" in res:
+        out["solve_ratio_fp32polish_over_fp64"] = res["fp64"]["solve_ms"] / res["fp32_polish"]["solve_ms"]
+        out["step_ratio_fp32polish_over_fp64"] = res["fp64"]["step_ms"] / res["fp32_polish"]["step_ms"]
+    if main_form == "fp32_polish":
+        out["roofline"]["peak_nonpacked"] = PEAK_FP32_NONPACKED / 1e12
+        out["roofline"]["frac_nonpacked"] = achieved / PEAK_FP32_NONPACKED
+    if not args.no_cpu_baseline and args.profile_only is None:
+        log("cpu baseline (oracle)")
+        cb, oroots, ns = cpu_baseline(a_host)
+        out["cpu_baseline"] = cb
+        # accuracy of both forms on the oracle's sample
+        import itertools
+        perms = np.array(list(itertools.permutations(range(6))))
+        sel = np.arange(0, ns, max(1, ns // 20000))
+        errs = {}
+        for form in ("fp32_polish", "fp64"):
+            rr, ss = pr.solve(a[:, :ns].contiguous(), None, form)
+            rr = rr.cpu().numpy()[:, sel]
+            ss = ss.cpu().numpy()[sel]
+            ref = oroots[:, sel]
+            cost = np.abs(rr[:, None, :] - ref[None, :, :]) ** 2
+            tot = cost[perms, np.arange(6)[None, :], :].sum(axis=1)
+            best = perms[np.argmin(tot, axis=0)].T
+            mm = np.take_along_axis(rr, best, axis=0)
+            e = np.abs(mm - ref) / np.abs(ref)
+            ok = ss == 0
+            errs[form] = {"max_rel_err_unflagged": float(e[:, ok].max()),
+                          "flagged": int((~ok).sum()), "checked_polys": int(sel.size)}
+        out["accuracy_vs_oracle"] = errs
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * proots.h -- C ABI of the batched polynomial-root library for AMD MI355X
+ * (gfx950).
+ *
+ * The library computes, for a batch of complex polynomials of degree <= 6,
+ * every root as an eigenvalue of the polynomial's Frobenius companion
+ * matrix (Tang & Quan, arXiv 2507.02164, Sec. II-B) by single-shift QR
+ * iteration (Alg. 1) realised with complex Givens rotations applied in
+ * place, two rows then two columns at a time (Sec. II-C, loop shape of
+ * Alg. 2), with bottom deflation.  The roots can then be counted into a
+ * root-density image (Sec. III, roots converted to pixel coordinates and
+ * accumulated in video memory), and root cotangents can be pulled back to
+ * coefficient cotangents with the implicit-function adjoint (not in the
+ * paper).
+ *
+ * Conventions shared by every call:
+ *   - Every array pointer is a DEVICE pointer (hipMalloc'ed or equivalent),
+ *     owned by the caller.  The library never allocates, frees or retains
+ *     caller memory.
+ *   - Complex numbers are pr_complex: two doubles (re, im), layout-identical
+ *     to std::complex<double>, C99 double complex and torch.complex128.
+ *   - Batched arrays are structures of arrays: element (k, i) of a [rows][n]
+ *     array is at offset k * n + i.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call only
+ *     enqueues work on it and returns; nothing synchronises the device.
+ *   - With n == 0 nothing is enqueued and the per-polynomial array pointers
+ *     may be NULL.
+ *   - The return value reports argument errors, detected on the host before
+ *     anything is enqueued, and kernel-launch failures.  Numerical outcomes
+ *     per polynomial are reported only through `status` bits, never as
+ *     errors.
+ *   - Calls are deterministic for identical inputs and options.
+ *   - No call throws across the ABI.
+ */
+#ifndef PROOTS_H
+#define PROOTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One complex double: (re, im). */
+typedef struct pr_complex {
+    double re;
+    double im;
+} pr_complex;
+
+/* Return codes. */
+enum pr_error {
+    PR_OK = 0,
+    PR_ERR_INVALID_ARG = -1,  /* a NULL pointer, n < 0, dmax out of range, bad window, ... */
+    PR_ERR_UNSUPPORTED = -2,  /* option value the library does not implement */
+    PR_ERR_HIP = -3           /* the HIP runtime refused the launch */
+};
+
+/* Per-polynomial status bits (uint32).  0 = every root computed normally. */
+enum pr_status_bits {
+    PR_ST_BAD_DEGREE = 1u << 0,        /* degree outside [1, dmax]; roots NaN */
+    PR_ST_NONFINITE = 1u << 1,         /* some a_k (k <= degree) is Inf or NaN; roots NaN */
+    PR_ST_ZERO_LEADING = 1u << 2,      /* a_degree == 0; roots NaN */
+    PR_ST_NOT_CONVERGED = 1u << 3,     /* a level hit the iteration cap and was deflated anyway */
+    PR_ST_POLISH_UNCONVERGED = 1u << 4,/* FP32 form: a Newton polish did not settle, or two
+                                          polished roots coincide */
+    PR_ST_SINGULAR_DERIV = 1u << 5     /* backward: p'(r) zero or non-finite at some root; that
+                                          root contributed nothing */
+};
+
+/* Arithmetic of the QR sweeps. */
+typedef enum pr_precision {
+    PR_FP64 = 0,          /* sweeps, deflation test and roots in FP64 */
+    PR_FP32_POLISH = 1    /* sweeps in FP32; deflation test in FP64; every root then polished
+                             by Newton steps in FP64 on the original polynomial */
+} pr_precision;
+
+/* Option flags. */
+enum pr_solve_flags {
+    PR_FLAG_NO_EXCEPTIONAL_SHIFT = 1u << 0  /* debug: pure Rayleigh shift only (a polynomial
+                                               such as z^d - c then stalls to the cap) */
+};
+
+/* Options of pr_solve.  Zero-initialised = defaults. */
+typedef struct pr_solve_opts {
+    int32_t precision;            /* pr_precision */
+    int32_t max_iter_per_level;   /* QR steps per deflation level before NOT_CONVERGED;
+                                     0 = 30; valid 1..1000 */
+    int32_t polish_steps;         /* FP32 form: Newton steps per root; 0 = 2; valid 1..8 */
+    uint32_t flags;               /* pr_solve_flags */
+    double polish_tol;            /* FP32 form: POLISH_UNCONVERGED when the last Newton step
+                                     exceeds polish_tol * |r|; 0 = 1e-6; valid (0, 1) */
+    int32_t* iter_counts;         /* optional DEVICE array [dmax-1][n] (row m-2 = QR steps
+                                     taken at level m), or NULL */
+} pr_solve_opts;
+
+/*
+ * pr_solve -- roots of n polynomials.
+ *
+ *   coeffs   [dmax+1][n] pr_complex, row k = a_k of p_i(z) = sum_k a_k z^k.
+ *            Rows above a polynomial's degree are not read.  Any nonzero
+ *            leading coefficient a_d is accepted (the polynomial is divided
+ *            by it first, Sec. II-B).
+ *   degrees  [n] int32 degree of each polynomial, or NULL (= all dmax).
+ *   n        number of polynomials, >= 0 (0 = no work).
+ *   dmax     1..6: row count of the arrays (coeffs has dmax+1 rows).
+ *   roots    [dmax][n] pr_complex out: the roots in deflation order (the
+ *            last diagonal entry found first, Alg. 1), NaN for rows >= the
+ *            polynomial's degree.  Must not alias coeffs.
+ *   status   [n] uint32 out: pr_status_bits.
+ *   opts     NULL = defaults (FP64).
+ * Errors: PR_ERR_INVALID_ARG for a NULL coeffs/roots/status, n < 0, dmax
+ * outside 1..6 or an option out of range; PR_ERR_HIP if a launch fails.
+ */
+int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_t n, int32_t dmax,
+             pr_complex* roots, uint32_t* status, const pr_solve_opts* opts, void* stream);
+
+/*
+ * pr_density -- count roots into a root-density image (Sec. III: the roots
+ * are converted to pixel coordinates and written into video memory).
+ *
+ * The window [x0, x1) x [y0, y1) of the complex plane is split into
+ * width x height pixels; row 0 holds the lowest imaginary parts.  With
+ * sx = width / (x1 - x0) and sy = height / (y1 - y0), computed once in FP64
+ * on the host, a root z counts iff u = (Re z - x0) * sx and
+ * v = (Im z - y0) * sy (each a correctly rounded FP64 subtract then
+ * multiply, never fused) satisfy 0 <= u < width and 0 <= v < height; it
+ * adds 1 to hist[floor(v)][floor(u)].  NaN roots never count.
+ *
+ *   roots      [dmax][n] pr_complex (as written by pr_solve).
+ *   degrees    [n] int32 or NULL: only rows k < degree are read.
+ *   status     [n] uint32 or NULL: polynomials with (status & skip_mask) != 0
+ *              are skipped.
+ *   hist       [height][width] int32, ACCUMULATED into (the caller zeroes it).
+ * Errors: PR_ERR_INVALID_ARG for NULL roots/hist, n < 0, dmax outside 1..6,
+ * non-finite window bounds, x1 <= x0, y1 <= y0, width or height <= 0, or an
+ * image larger than 2^31 - 1 pixels; PR_ERR_HIP if a launch fails.
+ */
+int pr_density(const pr_complex* roots, const int32_t* degrees, const uint32_t* status,
+               uint32_t skip_mask, int64_t n, int32_t dmax, double x0, double x1, double y0,
+               double y1, int32_t width, int32_t height, int32_t* hist, void* stream);
+
+/*
+ * pr_backward -- coefficient cotangents from root cotangents.
+ *
+ * At a simple root r of p, p(r(a); a) = 0 gives dr/da_k = -r^k / p'(r).
+ * With root cotangents in PyTorch's convention g_r = dL/dRe r + i dL/dIm r
+ * of a real loss L, the coefficient cotangent is
+ *     grad_a_k = sum_j conj(-r_j^k / p'(r_j)) * g_{r_j},   k = 0..degree,
+ * and 0 for rows k > degree.
+ *
+ *   coeffs       [dmax+1][n], degrees [n] or NULL, roots [dmax][n] as for
+ *                pr_solve (the roots are taken as given).
+ *   grad_roots   [dmax][n] pr_complex root cotangents (rows >= degree unread).
+ *   grad_coeffs  [dmax+1][n] pr_complex out.
+ *   status       [n] uint32 in/out: polynomials with BAD_DEGREE, NONFINITE
+ *                or ZERO_LEADING get zero gradient; a root where p'(r) is
+ *                zero or non-finite contributes nothing and SINGULAR_DERIV
+ *                is or-ed in.
+ * Errors: PR_ERR_INVALID_ARG for a NULL array argument (other than degrees),
+ * n < 0 or dmax outside 1..6; PR_ERR_HIP if a launch fails.
+ */
+int pr_backward(const pr_complex* coeffs, const int32_t* degrees, const pr_complex* roots,
+                const pr_complex* grad_roots, int64_t n, int32_t dmax, pr_complex* grad_coeffs,
+                uint32_t* status, void* stream);
+
+/* Static English text for a return code. */
+const char* pr_strerror(int code);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int pr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROOTS_H */

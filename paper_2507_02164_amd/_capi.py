@@ -1,0 +1,195 @@
+"""ctypes binding of the C ABI in include/proots.h.
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the computation runs in the HIP library.  There is no
+CPU fallback -- without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libproots.so")
+
+PR_OK = 0
+PR_ERR_INVALID_ARG = -1
+PR_ERR_UNSUPPORTED = -2
+PR_ERR_HIP = -3
+
+ST_BAD_DEGREE = 1 << 0
+ST_NONFINITE = 1 << 1
+ST_ZERO_LEADING = 1 << 2
+ST_NOT_CONVERGED = 1 << 3
+ST_POLISH_UNCONVERGED = 1 << 4
+ST_SINGULAR_DERIV = 1 << 5
+
+FP64 = 0
+FP32_POLISH = 1
+PRECISIONS = {"fp64": FP64, "fp32_polish": FP32_POLISH}
+
+FLAG_NO_EXCEPTIONAL_SHIFT = 1 << 0
+
+
+class ProotsError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+
+
+class SolveOpts(ctypes.Structure):
+    """Mirror of pr_solve_opts."""
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("max_iter_per_level", ctypes.c_int32),
+        ("polish_steps", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("polish_tol", ctypes.c_double),
+        ("iter_counts", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libproots.so (built by ``python -m paper_2507_02164_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2507_02164_amd.build` "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, U32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+        L.pr_solve.argtypes = [P, P, I64, I32, P, P, ctypes.POINTER(SolveOpts), P]
+        L.pr_solve.restype = ctypes.c_int
+        L.pr_density.argtypes = [P, P, P, U32, I64, I32, D, D, D, D, I32, I32, P, P]
+        L.pr_density.restype = ctypes.c_int
+        L.pr_backward.argtypes = [P, P, P, P, I64, I32, P, P, P]
+        L.pr_backward.restype = ctypes.c_int
+        L.pr_strerror.argtypes = [ctypes.c_int]
+        L.pr_strerror.restype = ctypes.c_char_p
+        L.pr_version.argtypes = []
+        L.pr_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().pr_strerror(code).decode()
+
+
+def version() -> int:
+    return lib().pr_version()
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=0, polish_steps=0,
+          polish_tol=0.0, flags=0, iter_counts=False, roots=None, status=None, stream=None):
+    """Roots of each column of ``coeffs`` (complex128 [dmax+1, n], row k =
+    a_k).  Returns ``(roots complex128 [dmax, n], status int32 [n])``, plus
+    the per-level QR step counts int32 [dmax-1, n] when ``iter_counts``.
+    Status bits are the ST_* constants (the int32 holds the uint32 bits)."""
+    _check(coeffs, "coeffs", torch.complex128)
+    if coeffs.dim() != 2:
+        raise ValueError("coeffs must be 2-D [dmax+1, n]")
+    dmax = coeffs.shape[0] - 1
+    n = coeffs.shape[1]
+    dev = coeffs.device
+    if degrees is not None:
+        _check(degrees, "degrees", torch.int32, (n,))
+    if roots is None:
+        roots = torch.empty((max(dmax, 0), n), dtype=torch.complex128, device=dev)
+    _check(roots, "roots", torch.complex128, (dmax, n))
+    if status is None:
+        status = torch.empty((n,), dtype=torch.int32, device=dev)
+    _check(status, "status", torch.int32, (n,))
+    its = None
+    if iter_counts:
+        its = torch.empty((max(dmax - 1, 0), n), dtype=torch.int32, device=dev)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    opts = SolveOpts(prec, max_iter_per_level, polish_steps, flags, polish_tol,
+                     None if its is None or its.numel() == 0 else its.data_ptr())
+    with torch.cuda.device(dev):
+        rc = lib().pr_solve(_ptr(coeffs), _ptr(degrees), n, dmax, _ptr(roots), _ptr(status),
+                            ctypes.byref(opts), _stream(stream))
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_solve")
+    if iter_counts:
+        return roots, status, its
+    return roots, status
+
+
+def density(roots, window, shape, degrees=None, status=None, skip_mask=0, out=None, stream=None):
+    """Count roots into an int32 [height, width] image over the half-open
+    window (x0, x1, y0, y1); row 0 holds the lowest imaginary parts.  Counts
+    are added to ``out`` when given (a new zeroed image otherwise)."""
+    _check(roots, "roots", torch.complex128)
+    if roots.dim() != 2:
+        raise ValueError("roots must be 2-D [dmax, n]")
+    dmax, n = roots.shape
+    x0, x1, y0, y1 = (float(v) for v in window)
+    width, height = (int(v) for v in shape)
+    if out is None:
+        out = torch.zeros((height, width), dtype=torch.int32, device=roots.device)
+    _check(out, "out", torch.int32, (height, width))
+    if degrees is not None:
+        _check(degrees, "degrees", torch.int32, (n,))
+    if status is not None:
+        _check(status, "status", torch.int32, (n,))
+    with torch.cuda.device(roots.device):
+        rc = lib().pr_density(_ptr(roots), _ptr(degrees), _ptr(status), skip_mask & 0xFFFFFFFF, n,
+                              dmax, x0, x1, y0, y1, width, height, _ptr(out), _stream(stream))
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_density")
+    return out
+
+
+def backward(coeffs, roots, grad_roots, degrees=None, status=None, grad_coeffs=None, stream=None):
+    """Coefficient cotangents from root cotangents (PyTorch's convention
+    dL/dRe + i dL/dIm).  ``status`` (int32 [n]) is read and SINGULAR_DERIV is
+    or-ed into it in place; a zero status is used when it is None.  Returns
+    ``(grad_coeffs complex128 [dmax+1, n], status)``."""
+    _check(coeffs, "coeffs", torch.complex128)
+    dmax = coeffs.shape[0] - 1
+    n = coeffs.shape[1]
+    _check(roots, "roots", torch.complex128, (dmax, n))
+    _check(grad_roots, "grad_roots", torch.complex128, (dmax, n))
+    if degrees is not None:
+        _check(degrees, "degrees", torch.int32, (n,))
+    if status is None:
+        status = torch.zeros((n,), dtype=torch.int32, device=coeffs.device)
+    _check(status, "status", torch.int32, (n,))
+    if grad_coeffs is None:
+        grad_coeffs = torch.empty_like(coeffs)
+    _check(grad_coeffs, "grad_coeffs", torch.complex128, (dmax + 1, n))
+    with torch.cuda.device(coeffs.device):
+        rc = lib().pr_backward(_ptr(coeffs), _ptr(degrees), _ptr(roots), _ptr(grad_roots), n, dmax,
+                               _ptr(grad_coeffs), _ptr(status), _stream(stream))
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_backward")
+    return grad_coeffs, status

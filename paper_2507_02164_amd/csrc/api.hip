@@ -1,0 +1,142 @@
+// api.hip -- the C ABI declared in include/proots.h: argument validation on
+// the host, then one kernel launch on the caller's stream.  Nothing here
+// allocates, synchronises or throws.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.hpp"
+#include "proots.h"
+
+using namespace proots;
+
+namespace {
+
+constexpr int kDefaultCap = 30;
+constexpr int kDefaultPolishSteps = 2;
+constexpr double kDefaultPolishTol = 1e-6;
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? PR_OK : PR_ERR_HIP; }
+
+}  // namespace
+
+extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_t n,
+                        int32_t dmax, pr_complex* roots, uint32_t* status,
+                        const pr_solve_opts* opts, void* stream)
+{
+    if (n < 0 || dmax < 1 || dmax > 6)
+        return PR_ERR_INVALID_ARG;
+    if (n > 0 && (!coeffs || !roots || !status))
+        return PR_ERR_INVALID_ARG;
+    pr_solve_opts o{};
+    if (opts)
+        o = *opts;
+    if (o.precision != PR_FP64 && o.precision != PR_FP32_POLISH)
+        return PR_ERR_UNSUPPORTED;
+    if (o.max_iter_per_level < 0 || o.max_iter_per_level > 1000)
+        return PR_ERR_INVALID_ARG;
+    if (o.polish_steps < 0 || o.polish_steps > 8)
+        return PR_ERR_INVALID_ARG;
+    if (!(o.polish_tol >= 0.0 && o.polish_tol < 1.0))
+        return PR_ERR_INVALID_ARG;
+    if (o.flags & ~(uint32_t)PR_FLAG_NO_EXCEPTIONAL_SHIFT)
+        return PR_ERR_UNSUPPORTED;
+    if (n == 0)
+        return PR_OK;
+    if (n > (int64_t)0x7fffffff * 256)
+        return PR_ERR_INVALID_ARG;
+    SolveArgs a;
+    a.coeffs = coeffs;
+    a.degrees = degrees;
+    a.n = n;
+    a.dmax = dmax;
+    a.roots = roots;
+    a.status = status;
+    a.iters = o.iter_counts;
+    a.cap = o.max_iter_per_level ? o.max_iter_per_level : kDefaultCap;
+    a.flags = o.flags;
+    a.polish_steps = o.polish_steps ? o.polish_steps : kDefaultPolishSteps;
+    a.polish_tol = o.polish_tol > 0.0 ? o.polish_tol : kDefaultPolishTol;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (o.precision == PR_FP64)
+        return hip_status(launch_solve_fp64(a, s));
+    return hip_status(launch_solve_fp32_polish(a, s));
+}
+
+extern "C" int pr_density(const pr_complex* roots, const int32_t* degrees,
+                          const uint32_t* status, uint32_t skip_mask, int64_t n, int32_t dmax,
+                          double x0, double x1, double y0, double y1, int32_t width,
+                          int32_t height, int32_t* hist, void* stream)
+{
+    if (n < 0 || dmax < 1 || dmax > 6 || !hist)
+        return PR_ERR_INVALID_ARG;
+    if (n > 0 && !roots)
+        return PR_ERR_INVALID_ARG;
+    if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(y0) || !std::isfinite(y1))
+        return PR_ERR_INVALID_ARG;
+    if (!(x1 > x0) || !(y1 > y0) || width <= 0 || height <= 0)
+        return PR_ERR_INVALID_ARG;
+    if ((int64_t)width * (int64_t)height > 0x7fffffffLL)
+        return PR_ERR_INVALID_ARG;
+    const double sx = (double)width / (x1 - x0);
+    const double sy = (double)height / (y1 - y0);
+    if (!std::isfinite(sx) || !std::isfinite(sy))
+        return PR_ERR_INVALID_ARG;
+    if (n == 0)
+        return PR_OK;
+    if (n > (int64_t)0x7fffffff * 256)
+        return PR_ERR_INVALID_ARG;
+    DensityArgs a;
+    a.roots = roots;
+    a.degrees = degrees;
+    a.status = status;
+    a.skip_mask = skip_mask;
+    a.n = n;
+    a.dmax = dmax;
+    a.x0 = x0;
+    a.y0 = y0;
+    a.sx = sx;
+    a.sy = sy;
+    a.width = width;
+    a.height = height;
+    a.hist = hist;
+    return hip_status(launch_density(a, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" int pr_backward(const pr_complex* coeffs, const int32_t* degrees,
+                           const pr_complex* roots, const pr_complex* grad_roots, int64_t n,
+                           int32_t dmax, pr_complex* grad_coeffs, uint32_t* status,
+                           void* stream)
+{
+    if (n < 0 || dmax < 1 || dmax > 6)
+        return PR_ERR_INVALID_ARG;
+    if (n > 0 && (!coeffs || !roots || !grad_roots || !grad_coeffs || !status))
+        return PR_ERR_INVALID_ARG;
+    if (n == 0)
+        return PR_OK;
+    if (n > (int64_t)0x7fffffff * 256)
+        return PR_ERR_INVALID_ARG;
+    BackwardArgs a;
+    a.coeffs = coeffs;
+    a.degrees = degrees;
+    a.roots = roots;
+    a.grad_roots = grad_roots;
+    a.n = n;
+    a.dmax = dmax;
+    a.grad_coeffs = grad_coeffs;
+    a.status = status;
+    return hip_status(launch_backward(a, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" const char* pr_strerror(int code)
+{
+    switch (code) {
+    case PR_OK: return "success";
+    case PR_ERR_INVALID_ARG: return "invalid argument";
+    case PR_ERR_UNSUPPORTED: return "unsupported option";
+    case PR_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown error code";
+}
+
+extern "C" int pr_version(void) { return 100; }

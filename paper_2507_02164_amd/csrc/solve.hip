@@ -1,0 +1,526 @@
+// solve.hip -- batched polynomial roots by single-shift QR iteration on the
+// Frobenius companion matrix, one polynomial per lane (gfx950).
+//
+// Method (arXiv 2507.02164):
+//   Sec. II-B   the roots of z^d + b_{d-1} z^{d-1} + ... + b_0 are the
+//               eigenvalues of its companion matrix; Alg. 1 finds them by
+//               single-shift QR iteration with bottom deflation.
+//   Sec. II-C   each QR step A - sI = QR, A <- RQ + sI is done in place:
+//               complex Givens rotations [[c, s], [-conj s, conj c]] that map
+//               (a, b) to (sqrt(|a|^2 + |b|^2), 0) are applied to two rows at
+//               a time, then their conjugate transposes to two columns at a
+//               time; the Appendix shows the matrix stays upper Hessenberg.
+//
+// GPU design:
+//   * One polynomial per lane.  The active upper-Hessenberg matrix lives in
+//     VGPRs as a band (on/above-diagonal entries plus the subdiagonal: 26
+//     complex entries at degree 6).  Every index is a compile-time constant:
+//     the level m is a template parameter and all loops are unrolled, so no
+//     entry is ever addressed at run time (no scratch).
+//   * Loops are trimmed to the band: in the row pass of rotation r only
+//     columns r-1..m-1 of rows r-1, r are nonzero; in the column pass only
+//     rows 0..r of columns r-1, r.  The entry a rotation annihilates is
+//     stored as an exact zero and the diagonal entry it produces as the real
+//     rho.  The skipped products are products with exact zeros, so this is
+//     the same arithmetic as the dense loops of Alg. 2.
+//   * The column rotation r-1 is applied right after the row rotation r (a
+//     lag of one): it touches only rows <= r-1 and the entry (r-1, r-1)
+//     that row rotation r has just finished, so every operation sees the
+//     same operands as in the row-pass-then-column-pass order, while only
+//     two Givens pairs are live at a time.
+//   * Convergence (the paper uses a fixed count): level m deflates once
+//     cabs1(h[m-1][m-2]) <= eps (cabs1(h[m-1][m-1]) + cabs1(h[m-2][m-2])),
+//     evaluated in FP64, eps = 2^-52 for FP64 sweeps and 2^-23 for FP32
+//     sweeps.  Exceptional shift s += cabs1(h[m-1][m-2]) (0.75 + 0.5i) on the
+//     10th and 20th step of a level; after `cap` steps the level deflates
+//     anyway and NOT_CONVERGED is set.
+//   * FP32 form: sweeps in FP32, test in FP64, then every root is polished
+//     by Newton steps r <- r - p(r)/p'(r) in FP64 on the original
+//     coefficients.
+#include <hip/hip_runtime.h>
+
+#include "cplx.hpp"
+#include "internal.hpp"
+
+namespace proots {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------- Givens
+// (c, s) = (conj a, conj b) / rho, rho = sqrt(|a|^2 + |b|^2): the only pair
+// for which the Sec. II-C rotation maps (a, b) to (rho, 0).  rho == 0 gives
+// the identity.  Branch-free (a branch here would split the fully unrolled
+// QR step into basic blocks and stretch register lifetimes across them); the
+// price is the range: |a|^2 + |b|^2 must not overflow (entries below about
+// 1e154 in FP64, 1e19 in FP32), otherwise NaN propagates and the level ends
+// NOT_CONVERGED.
+__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
+__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+
+// Scalar select on values already computed (a conditional operator on a
+// struct, or on an expression, may be emitted as a branch).
+template <typename T>
+__device__ __forceinline__ T pick(bool p, T a, T b)
+{
+    return p ? a : b;
+}
+
+template <typename T>
+__device__ __forceinline__ void givens(cx<T> a, cx<T> b, cx<T>& c, cx<T>& s, T& rho)
+{
+    const T n2 = a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im;
+    const T inv = rsqrt_t(n2);
+    const bool z = !(n2 > T(0));
+    const T r = n2 * inv;
+    const T cr = a.re * inv, ci = -a.im * inv, sr = b.re * inv, si = -b.im * inv;
+    rho = pick(z, T(0), r);
+    c = {pick(z, T(1), cr), pick(z, T(0), ci)};
+    s = {pick(z, T(0), sr), pick(z, T(0), si)};
+}
+
+// (x, y) <- (c x + s y, -conj(s) x + conj(c) y): rows r-1, r (Alg. 2 row loop).
+template <typename T>
+__device__ __forceinline__ void rot_rows(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s)
+{
+    T xr = x.re, xi = x.im, yr = y.re, yi = y.im;
+    x.re = c.re * xr - c.im * xi + s.re * yr - s.im * yi;
+    x.im = c.re * xi + c.im * xr + s.re * yi + s.im * yr;
+    y.re = c.re * yr + c.im * yi - s.re * xr - s.im * xi;
+    y.im = c.re * yi - c.im * yr - s.re * xi + s.im * xr;
+}
+
+// (x, y) <- (conj(c) x + conj(s) y, -s x + c y): columns r-1, r (Alg. 2 column loop).
+template <typename T>
+__device__ __forceinline__ void rot_cols(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s)
+{
+    T xr = x.re, xi = x.im, yr = y.re, yi = y.im;
+    x.re = c.re * xr + c.im * xi + s.re * yr + s.im * yi;
+    x.im = c.re * xi - c.im * xr + s.re * yi - s.im * yr;
+    y.re = c.re * yr - c.im * yi - s.re * xr + s.im * xi;
+    y.im = c.re * yi + c.im * yr - s.re * xi - s.im * xr;
+}
+
+// One shifted QR step on the leading M x M block (Alg. 1 body via Sec. II-C),
+// executed by every lane of the wave.  Lanes with act == false take the
+// identity rotation (c, s) = (1, 0) and shift 0 throughout, which leaves
+// their matrix unchanged bit for bit (1*x + 0*y == x); the entries a real
+// rotation overwrites are selected.  Running the step wave-uniformly, with no
+// lane-divergent branch around it, matters: a divergent branch would keep
+// the pre-step matrix of the lanes that skip it alive next to the post-step
+// matrix of the lanes that take it, doubling the register footprint.
+template <typename T, int DM, int M>
+__device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
+{
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        h[i][i].re -= sh.re;
+        h[i][i].im -= sh.im;
+    }
+    cx<T> cprev, sprev;
+#pragma unroll
+    for (int r = 1; r < M; ++r) {
+        cx<T> c, s;
+        T rho;
+        givens(h[r - 1][r - 1], h[r][r - 1], c, s, rho);
+        c = {pick(act, c.re, T(1)), pick(act, c.im, T(0))};
+        s = {pick(act, s.re, T(0)), pick(act, s.im, T(0))};
+        // the rotation maps (h[r-1][r-1], h[r][r-1]) to (rho, 0)
+        h[r - 1][r - 1] = {pick(act, rho, h[r - 1][r - 1].re), pick(act, T(0), h[r - 1][r - 1].im)};
+        h[r][r - 1] = {pick(act, T(0), h[r][r - 1].re), pick(act, T(0), h[r][r - 1].im)};
+#pragma unroll
+        for (int j = r; j < M; ++j)
+            rot_rows(h[r - 1][j], h[r][j], c, s);
+        if (r >= 2) {
+            // lagged column rotation r-1 on rows 0..r-1 (row r-1 enters with
+            // h[r-1][r-2] == 0 for acting lanes)
+#pragma unroll
+            for (int j = 0; j <= r - 1; ++j)
+                rot_cols(h[j][r - 2], h[j][r - 1], cprev, sprev);
+        }
+        cprev = c;
+        sprev = s;
+    }
+#pragma unroll
+    for (int j = 0; j <= M - 1; ++j)
+        rot_cols(h[j][M - 2], h[j][M - 1], cprev, sprev);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        h[i][i].re += sh.re;
+        h[i][i].im += sh.im;
+    }
+}
+
+template <typename T>
+struct Eps;
+template <>
+struct Eps<double> {
+    static constexpr double v = 0x1p-52;
+};
+template <>
+struct Eps<float> {
+    static constexpr double v = 0x1p-23;
+};
+
+// One trip at level M (wave-uniform).  A lane at level M whose bottom
+// subdiagonal entry is negligible, or that has used up its steps, deflates:
+// h[M-1][M-1] goes to `emit`, the step count is recorded and the lane drops
+// to level M-1.  Every other lane at level M takes one shifted QR step; lanes
+// below level M ride along with the identity.
+template <typename T, int DM, int M, typename Emit>
+__device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int cap, bool exc,
+                                     uint32_t& st, int32_t* __restrict__ iters, int64_t n,
+                                     int64_t i, Emit&& emit)
+{
+    const bool here = m == M;
+    const double hh = cabs1_d(h[M - 1][M - 2]);
+    const double tt = cabs1_d(h[M - 1][M - 1]) + cabs1_d(h[M - 2][M - 2]);
+    const bool conv = hh <= Eps<T>::v * tt;
+    const bool done = here && (conv || its == cap);
+    if (done) {
+        if (!conv)
+            st |= PR_ST_NOT_CONVERGED;
+        if (iters)
+            iters[(int64_t)(M - 2) * n + i] = its;
+        emit(M - 1, h[M - 1][M - 1]);
+    }
+    const bool act = here && !done;
+    const bool ex = exc && (its == 10 || its == 20);
+    const T ere = (T)((double)h[M - 1][M - 1].re + hh * 0.75);
+    const T eim = (T)((double)h[M - 1][M - 1].im + hh * 0.5);
+    const cx<T> sh = {pick(act, pick(ex, ere, h[M - 1][M - 1].re), T(0)),
+                      pick(act, pick(ex, eim, h[M - 1][M - 1].im), T(0))};
+    m = done ? M - 1 : m;
+    its = done ? 0 : its + (act ? 1 : 0);
+    qr_step<T, DM, M>(h, sh, act);
+}
+
+// Alg. 1's level loop for a wave of independent lanes, level by level: the
+// wave keeps taking trips at level M while any of its lanes is still at
+// level M (a wave-uniform condition), then moves on to M-1.  Lanes that
+// deflate early, or whose degree is below M, ride along with the identity.
+// Keeping the wave level-synchronous wastes less work on lane divergence
+// than letting every lane run its own level (a trip would then execute the
+// union of the levels present), and a separate loop per level lets each
+// loop carry only its own M x M block in registers.
+template <typename T, int DM, int M, typename Emit>
+__device__ __forceinline__ void iterate_from(cx<T> (&h)[DM][DM], int& m, int& its, int cap,
+                                             bool exc, uint32_t& st, int32_t* __restrict__ iters,
+                                             int64_t n, int64_t i, Emit&& emit)
+{
+    if constexpr (M >= 2) {
+        while (__ballot(m == M))
+            trip<T, DM, M>(h, m, its, cap, exc, st, iters, n, i, emit);
+        iterate_from<T, DM, M - 1>(h, m, its, cap, exc, st, iters, n, i, emit);
+    }
+}
+
+template <typename T, int DM, typename Emit>
+__device__ __forceinline__ void iterate(cx<T> (&h)[DM][DM], int d, int cap, bool exc,
+                                        uint32_t& st, int32_t* __restrict__ iters, int64_t n,
+                                        int64_t i, Emit&& emit)
+{
+    int m = d, its = 0;
+    iterate_from<T, DM, DM>(h, m, its, cap, exc, st, iters, n, i, emit);
+}
+
+// Companion matrix, first-row form: h[0][j] = -b_{d-1-j} for j < d, ones on
+// the subdiagonal of the leading d x d block.  Built from value selects on
+// the run-time degree, so every matrix entry is written at a fixed
+// location (a store whose address depended on d would force the matrix out
+// of registers).
+template <typename T, int DM>
+__device__ __forceinline__ void companion(cx<T> (&h)[DM][DM], int d,
+                                          const cx<double> (&b)[DM + 1])
+{
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        cx<double> v = {0.0, 0.0};
+#pragma unroll
+        for (int D = j + 1; D <= DM; ++D)
+            if (d == D)
+                v = b[D - 1 - j];
+        h[0][j] = {(T)(-v.re), (T)(-v.im)};
+    }
+#pragma unroll
+    for (int i = 1; i < DM; ++i)
+        h[i][i - 1] = {i < d ? T(1) : T(0), T(0)};
+}
+
+template <int DM>
+__device__ __forceinline__ void zero_iters(int32_t* iters, int64_t n, int64_t i)
+{
+    if (iters)
+#pragma unroll
+        for (int m = 2; m <= DM; ++m)
+            iters[(int64_t)(m - 2) * n + i] = 0;
+}
+
+// Load a_0..a_d (zeros above d), validate, and normalise to b = a / a_d.
+template <int DM>
+__device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs, int64_t n,
+                                              int64_t i, int d, cx<double> (&a)[DM + 1],
+                                              cx<double> (&b)[DM + 1])
+{
+    uint32_t st = 0;
+    cx<double> lead = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k <= DM; ++k) {
+        a[k] = {0.0, 0.0};
+        if (k <= d) {
+            double2 v = coeffs[(int64_t)k * n + i];
+            a[k] = {v.x, v.y};
+            if (!finite(a[k]))
+                st |= PR_ST_NONFINITE;
+        }
+        if (k == d)
+            lead = a[k];
+    }
+    if (!st && lead.re == 0.0 && lead.im == 0.0)
+        st |= PR_ST_ZERO_LEADING;
+    const bool monic = lead.re == 1.0 && lead.im == 0.0;
+#pragma unroll
+    for (int k = 0; k <= DM; ++k)
+        b[k] = (k < d && !monic) ? cdiv(a[k], lead) : a[k];
+    return st;
+}
+
+#ifndef PR_FP64_WAVES
+#define PR_FP64_WAVES 1
+#endif
+#ifndef PR_FP32_WAVES
+#define PR_FP32_WAVES 1
+#endif
+
+template <int DM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PR_FP64_WAVES))) void solve_fp64_kernel(
+    const double2* __restrict__ coeffs, const int32_t* __restrict__ degrees, int64_t n,
+    double2* __restrict__ roots, uint32_t* __restrict__ status, int32_t* __restrict__ iters,
+    int cap, uint32_t flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const int d = degrees ? degrees[i] : DM;
+    const double qnan = __builtin_nan("");
+#pragma unroll
+    for (int k = 0; k < DM; ++k)
+        if (k >= d)
+            roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
+    if (d < 1 || d > DM) {
+        status[i] = PR_ST_BAD_DEGREE;
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d)
+                roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
+        zero_iters<DM>(iters, n, i);
+        return;
+    }
+    cx<double> a[DM + 1], b[DM + 1];
+    uint32_t st = load_poly<DM>(coeffs, n, i, d, a, b);
+    if (st) {
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d)
+                roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
+        status[i] = st;
+        zero_iters<DM>(iters, n, i);
+        return;
+    }
+    cx<double> h[DM][DM];
+#pragma unroll
+    for (int r = 0; r < DM; ++r)
+#pragma unroll
+        for (int c = (r > 0 ? r - 1 : 0); c < DM; ++c)
+            h[r][c] = {0.0, 0.0};
+    companion<double, DM>(h, d, b);
+    if (iters)
+#pragma unroll
+        for (int m = 2; m <= DM; ++m)
+            if (m > d)
+                iters[(int64_t)(m - 2) * n + i] = 0;
+
+    const bool exc = !(flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT);
+    iterate<double, DM>(h, d, cap, exc, st, iters, n, i, [&](int k, cx<double> v) {
+        roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
+    });
+    roots[i] = make_double2(h[0][0].re, h[0][0].im);
+    status[i] = st;
+}
+
+// Newton polish in FP64 on the original coefficients a (zeros above the
+// degree, so Horner from DM gives the same value as from the degree).
+template <int DM>
+__device__ __forceinline__ cx<double> polish(cx<double> r, const cx<double> (&a)[DM + 1],
+                                             int steps, double& last2)
+{
+    last2 = 0.0;
+    for (int s = 0; s < steps; ++s) {
+        cx<double> p = a[DM], dp = {0.0, 0.0};
+#pragma unroll
+        for (int k = DM - 1; k >= 0; --k) {
+            dp = dp * r + p;
+            p = p * r + a[k];
+        }
+        double den = norm2(dp);
+        cx<double> delta = {0.0, 0.0};
+        if (den > 0.0 && isfinite(den)) {
+            cx<double> q = p * conj(dp);
+            double inv = 1.0 / den;
+            delta = {q.re * inv, q.im * inv};
+        }
+        r = r - delta;
+        last2 = norm2(delta);
+    }
+    return r;
+}
+
+template <int DM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PR_FP32_WAVES))) void solve_fp32_polish_kernel(
+    const double2* __restrict__ coeffs, const int32_t* __restrict__ degrees, int64_t n,
+    double2* __restrict__ roots, uint32_t* __restrict__ status, int32_t* __restrict__ iters,
+    int cap, uint32_t flags, int polish_steps, double polish_tol,
+    const double2* coeffs_again)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const int d = degrees ? degrees[i] : DM;
+    const double qnan = __builtin_nan("");
+    if (d < 1 || d > DM) {
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
+        status[i] = PR_ST_BAD_DEGREE;
+        zero_iters<DM>(iters, n, i);
+        return;
+    }
+    cx<double> a[DM + 1], b[DM + 1];
+    uint32_t st = load_poly<DM>(coeffs, n, i, d, a, b);
+    if (st) {
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
+        status[i] = st;
+        zero_iters<DM>(iters, n, i);
+        return;
+    }
+    cx<float> h[DM][DM];
+#pragma unroll
+    for (int r = 0; r < DM; ++r)
+#pragma unroll
+        for (int c = (r > 0 ? r - 1 : 0); c < DM; ++c)
+            h[r][c] = {0.0f, 0.0f};
+    companion<float, DM>(h, d, b);
+    if (iters)
+#pragma unroll
+        for (int m = 2; m <= DM; ++m)
+            if (m > d)
+                iters[(int64_t)(m - 2) * n + i] = 0;
+
+    cx<float> e[DM];
+#pragma unroll
+    for (int k = 0; k < DM; ++k)
+        e[k] = {0.0f, 0.0f};
+    const bool exc = !(flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT);
+    iterate<float, DM>(h, d, cap, exc, st, iters, n, i, [&](int k, cx<float> v) {
+        // k is a compile-time constant after inlining
+#pragma unroll
+        for (int q = 0; q < DM; ++q)
+            if (q == k)
+                e[q] = v;
+    });
+    e[0] = h[0][0];
+
+    // The original coefficients, read again (through a second pointer, so
+    // the compiler cannot keep the first load alive across the QR loop).
+#pragma unroll
+    for (int k = 0; k <= DM; ++k) {
+        a[k] = {0.0, 0.0};
+        if (k <= d) {
+            const double2 v = coeffs_again[(int64_t)k * n + i];
+            a[k] = {v.x, v.y};
+        }
+    }
+    cx<double> r[DM];
+    const double tol2 = polish_tol * polish_tol;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < DM; ++k) {
+        r[k] = {qnan, qnan};
+        if (k < d) {
+            double last2;
+            r[k] = polish<DM>(cx<double>{(double)e[k].re, (double)e[k].im}, a, polish_steps, last2);
+            if (!(last2 <= tol2 * norm2(r[k])))
+                bad = true;
+        }
+    }
+    // Two polished roots on top of each other: one root was lost.
+#pragma unroll
+    for (int j = 0; j < DM; ++j)
+#pragma unroll
+        for (int k = j + 1; k < DM; ++k)
+            if (k < d) {
+                double sep2 = norm2(r[j] - r[k]);
+                double mag = fmax(norm2(r[j]), 1.0) * 1e-16;  // (1e-8 max(|r_j|, 1))^2
+                if (sep2 <= mag)
+                    bad = true;
+            }
+    if (bad)
+        st |= PR_ST_POLISH_UNCONVERGED;
+#pragma unroll
+    for (int k = 0; k < DM; ++k)
+        roots[(int64_t)k * n + i] = make_double2(r[k].re, r[k].im);
+    status[i] = st;
+}
+
+template <int DM>
+hipError_t launch_fp64_dm(const SolveArgs& a, hipStream_t stream)
+{
+    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(solve_fp64_kernel<DM>, dim3((unsigned)blocks), dim3(kBlock), 0, stream,
+                       reinterpret_cast<const double2*>(a.coeffs), a.degrees, a.n,
+                       reinterpret_cast<double2*>(a.roots), a.status, a.iters, a.cap, a.flags);
+    return hipGetLastError();
+}
+
+template <int DM>
+hipError_t launch_fp32_dm(const SolveArgs& a, hipStream_t stream)
+{
+    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(solve_fp32_polish_kernel<DM>, dim3((unsigned)blocks), dim3(kBlock), 0,
+                       stream, reinterpret_cast<const double2*>(a.coeffs), a.degrees, a.n,
+                       reinterpret_cast<double2*>(a.roots), a.status, a.iters, a.cap, a.flags,
+                       a.polish_steps, a.polish_tol, reinterpret_cast<const double2*>(a.coeffs));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_solve_fp64(const SolveArgs& a, hipStream_t stream)
+{
+    switch (a.dmax) {
+    case 1: return launch_fp64_dm<1>(a, stream);
+    case 2: return launch_fp64_dm<2>(a, stream);
+    case 3: return launch_fp64_dm<3>(a, stream);
+    case 4: return launch_fp64_dm<4>(a, stream);
+    case 5: return launch_fp64_dm<5>(a, stream);
+    case 6: return launch_fp64_dm<6>(a, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_solve_fp32_polish(const SolveArgs& a, hipStream_t stream)
+{
+    switch (a.dmax) {
+    case 1: return launch_fp32_dm<1>(a, stream);
+    case 2: return launch_fp32_dm<2>(a, stream);
+    case 3: return launch_fp32_dm<3>(a, stream);
+    case 4: return launch_fp32_dm<4>(a, stream);
+    case 5: return launch_fp32_dm<5>(a, stream);
+    case 6: return launch_fp32_dm<6>(a, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace proots

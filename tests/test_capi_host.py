@@ -1,0 +1,140 @@
+"""The C ABI library loads, exports every symbol include/proots.h declares,
+and rejects bad arguments on the host before touching the GPU (CPU only:
+no call here launches a kernel)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "proots.h")
+LIB = os.path.join(ROOT, "paper_2507_02164_amd", "libproots.so")
+
+
+def _ensure_built():
+    if not os.path.exists(LIB):
+        from paper_2507_02164_amd import build
+        build.build()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    _ensure_built()
+    import paper_2507_02164_amd as pr
+    return pr.lib()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_calls():
+    names = _declared_functions()
+    for f in ("pr_solve", "pr_density", "pr_backward", "pr_strerror", "pr_version"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version(lib):
+    import paper_2507_02164_amd as pr
+    assert pr.strerror(0) == "success"
+    assert "invalid" in pr.strerror(-1)
+    assert pr.strerror(12345) == "unknown error code"
+    assert pr.version() >= 100
+
+
+def test_solve_argument_validation(lib):
+    import paper_2507_02164_amd as pr
+    P = ctypes.c_void_p
+    fake = P(0x1000)  # never dereferenced: validation fails first
+    opts = pr.SolveOpts()
+    assert lib.pr_solve(None, None, 10, 6, fake, fake, None, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_solve(fake, None, -1, 6, fake, fake, None, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_solve(fake, None, 10, 0, fake, fake, None, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_solve(fake, None, 10, 7, fake, fake, None, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_solve(fake, None, 10, 6, None, fake, None, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_solve(fake, None, 10, 6, fake, None, None, None) == pr.PR_ERR_INVALID_ARG
+    bad = pr.SolveOpts(precision=5)
+    assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
+    bad = pr.SolveOpts(max_iter_per_level=-3)
+    assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_INVALID_ARG
+    bad = pr.SolveOpts(polish_steps=9)
+    assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_INVALID_ARG
+    bad = pr.SolveOpts(polish_tol=2.0)
+    assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_INVALID_ARG
+    bad = pr.SolveOpts(flags=0x80)
+    assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
+    # n == 0 is a valid no-op: nothing is enqueued, the arrays may be NULL
+    assert lib.pr_solve(fake, None, 0, 6, fake, fake, ctypes.byref(opts), None) == pr.PR_OK
+    assert lib.pr_solve(None, None, 0, 6, None, None, None, None) == pr.PR_OK
+
+
+def test_density_argument_validation(lib):
+    import paper_2507_02164_amd as pr
+    fake = ctypes.c_void_p(0x1000)
+    ok = dict(x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, w=8, h=8)
+
+    def call(roots=fake, hist=fake, n=4, dmax=6, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, w=8, h=8):
+        return lib.pr_density(roots, None, None, 0, n, dmax, x0, x1, y0, y1, w, h, hist, None)
+
+    assert call(roots=None) == pr.PR_ERR_INVALID_ARG
+    assert call(hist=None) == pr.PR_ERR_INVALID_ARG
+    assert call(n=-1) == pr.PR_ERR_INVALID_ARG
+    assert call(dmax=7) == pr.PR_ERR_INVALID_ARG
+    assert call(x1=-1.0) == pr.PR_ERR_INVALID_ARG
+    assert call(y1=-2.0) == pr.PR_ERR_INVALID_ARG
+    assert call(w=0) == pr.PR_ERR_INVALID_ARG
+    assert call(h=-5) == pr.PR_ERR_INVALID_ARG
+    assert call(x0=float("nan")) == pr.PR_ERR_INVALID_ARG
+    assert call(x1=float("inf")) == pr.PR_ERR_INVALID_ARG
+    assert call(w=65536, h=65536) == pr.PR_ERR_INVALID_ARG
+    assert call(n=0) == pr.PR_OK
+    assert call(n=0, roots=None) == pr.PR_OK
+
+
+def test_backward_argument_validation(lib):
+    import paper_2507_02164_amd as pr
+    f = ctypes.c_void_p(0x1000)
+    assert lib.pr_backward(None, None, f, f, 4, 6, f, f, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_backward(f, None, None, f, 4, 6, f, f, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_backward(f, None, f, None, 4, 6, f, f, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_backward(f, None, f, f, 4, 6, None, f, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_backward(f, None, f, f, 4, 6, f, None, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_backward(f, None, f, f, -4, 6, f, f, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_backward(f, None, f, f, 4, 0, f, f, None) == pr.PR_ERR_INVALID_ARG
+    assert lib.pr_backward(f, None, f, f, 0, 6, f, f, None) == pr.PR_OK
+    assert lib.pr_backward(None, None, None, None, 0, 6, None, None, None) == pr.PR_OK
+
+
+def test_python_binding_refuses_cpu_tensors(lib):
+    import torch
+    import paper_2507_02164_amd as pr
+    c = torch.zeros((7, 4), dtype=torch.complex128)
+    with pytest.raises(ValueError, match="GPU"):
+        pr.solve(c)
+    with pytest.raises(ValueError, match="GPU"):
+        pr.density(torch.zeros((6, 4), dtype=torch.complex128), (-1, 1, -1, 1), (4, 4))
+
+
+def test_oracle_and_product_share_no_code():
+    """The oracle tree and the HIP tree include nothing of each other."""
+    import glob
+    prod = glob.glob(os.path.join(ROOT, "paper_2507_02164_amd", "**", "*.*"), recursive=True)
+    for f in prod:
+        if f.endswith((".py", ".hip", ".hpp", ".h")):
+            txt = open(f).read()
+            assert "import oracle" not in txt and "from oracle" not in txt, f
+            assert "oracle.c" not in txt and "liboracle" not in txt, f
+    for f in glob.glob(os.path.join(ROOT, "oracle", "*.*")):
+        if f.endswith((".py", ".c", ".h")):
+            txt = open(f).read()
+            assert "paper_2507_02164_amd" not in txt and "proots.h" not in txt, f

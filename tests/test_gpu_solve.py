@@ -1,0 +1,244 @@
+"""GPU parity of pr_solve against the oracle (run on an MI355X).
+
+Roots are compared after the optimal assignment per polynomial.  FP64 form:
+relative error <= 1e-10, or, for a root whose relative condition number
+kappa makes 1e-10 unreachable in FP64, <= 1e3 kappa u (the rounding floor
+both sides share).  FP32 + FP64-polish form: every root of a polynomial
+without POLISH_UNCONVERGED within the same bound; flagged polynomials are
+counted and bounded separately.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpuutil import parity_bound, rel_condition, to_dev, to_host
+from rootmatch import match, match_mixed, rel_err, valid_mask
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pr = pytest.importorskip("paper_2507_02164_amd")
+
+
+def _solve(a, deg=None, precision="fp64", **kw):
+    out = pr.solve(to_dev(a), None if deg is None else to_dev(deg), precision, **kw)
+    torch.cuda.synchronize()
+    return tuple(to_host(t) for t in out)
+
+
+def _check_roots(got, st, a, deg, ref, ref_st, floor=1e-10, flagged_ok=False):
+    """Assert parity; returns (max relative error over checked roots,
+    fraction of polynomials flagged)."""
+    dmax, n = ref.shape
+    m = match(got, ref) if deg is None else match_mixed(got, ref, deg)
+    valid = valid_mask(dmax, deg, n)
+    kappa = rel_condition(a, ref, deg)
+    err = rel_err(m, ref)
+    bound = parity_bound(kappa, floor)
+    ok_poly = (ref_st == 0)
+    flagged = (st & pr.ST_POLISH_UNCONVERGED) != 0
+    check = valid & ok_poly[None, :]
+    if flagged_ok:
+        check &= ~flagged[None, :]
+    bad = check & ~(err <= bound)
+    assert not bad.any(), (f"{bad.sum()} roots out of bound; worst err {err[bad].max():.3e} "
+                           f"kappa {kappa[bad][np.argmax(err[bad])]:.3e}")
+    # rows beyond the degree are NaN
+    assert np.all(np.isnan(got[~valid]))
+    return float(err[check].max()), float(flagged.mean())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
+def test_gaussian_full(precision):
+    """65,536 monic degree-6 polynomials with standard complex normal
+    coefficients, every root."""
+    a = workloads.gaussian(65536, seed=0)
+    ref, ref_st = oracle.solve(a)
+    got, st = _solve(a, None, precision)
+    assert np.all(ref_st == 0)
+    if precision == "fp64":
+        assert np.all(st == 0)
+    else:
+        assert np.all((st & ~pr.ST_POLISH_UNCONVERGED) == 0)
+    worst, flagged = _check_roots(got, st, a, None, ref, ref_st, flagged_ok=precision != "fp64")
+    print(f"\n{precision}: worst rel err {worst:.3e}, flagged {flagged:.2e}")
+    assert flagged < 1e-3
+    assert worst < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
+def test_parametric_grid(precision):
+    a = workloads.parametric(256, seed=0)
+    ref, ref_st = oracle.solve(a)
+    got, st = _solve(a, None, precision)
+    worst, flagged = _check_roots(got, st, a, None, ref, ref_st, flagged_ok=precision != "fp64")
+    assert flagged < 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
+def test_mixed_degree(precision):
+    """Degrees 2..6 in one batch, log-uniform moduli; FP32 + polish within
+    1e-8 of the FP64 oracle on every polynomial."""
+    a, deg = workloads.mixed(50000, seed=3)
+    ref, ref_st = oracle.solve(a, deg)
+    got, st = _solve(a, deg, precision)
+    floor = 1e-10 if precision == "fp64" else 1e-8
+    worst, flagged = _check_roots(got, st, a, deg, ref, ref_st, floor=floor,
+                                  flagged_ok=precision != "fp64")
+    print(f"\n{precision}: worst {worst:.3e} flagged {flagged:.2e}")
+    assert flagged < 1e-2
+
+
+def test_known_roots_against_truth():
+    coeffs, roots, _ = workloads.known_roots(20000, seed=0)
+    got, st = _solve(coeffs, None, "fp64")
+    assert np.all(st == 0)
+    m = match(got, roots)
+    kappa = rel_condition(coeffs, roots)
+    err = rel_err(m, roots)
+    # the generating roots are exact only up to the rounding of the expanded
+    # coefficients (relative u per coefficient), hence a kappa-scaled bound
+    assert np.all(err <= np.maximum(1e-12, 64 * kappa * 2.0 ** -53))
+
+
+def test_clustered_classes():
+    """Three roots within 1e-3 of each other: FP64 resolves the cluster to
+    the rounding floor kappa u; the isolated roots and the cluster centroid
+    stay within 1e-9.  FP32 + polish flags (nearly) every cluster."""
+    coeffs, roots = workloads.clustered(8192, seed=0)
+    ref, ref_st = oracle.solve(coeffs)
+    got, st = _solve(coeffs, None, "fp64")
+    kappa = rel_condition(coeffs, ref)
+    m = match(got, ref)
+    err = rel_err(m, ref)
+    assert np.all(err <= parity_bound(kappa, 1e-9, c=1e4))
+    g32, s32 = _solve(coeffs, None, "fp32_polish")
+    flagged = (s32 & pr.ST_POLISH_UNCONVERGED) != 0
+    assert flagged.mean() > 0.5
+    ok = ~flagged
+    if ok.any():
+        e32 = rel_err(match(g32[:, ok], ref[:, ok]), ref[:, ok])
+        assert np.all(e32 <= parity_bound(kappa[:, ok], 1e-9, c=1e4))
+
+
+@pytest.mark.parametrize("n", [1, 7, 255, 257, 1000])
+def test_ragged_sizes(n):
+    a = workloads.gaussian(n, seed=n)
+    ref, _ = oracle.solve(a)
+    for precision in ("fp64", "fp32_polish"):
+        got, st = _solve(a, None, precision)
+        assert got.shape == (6, n)
+        assert rel_err(match(got, ref), ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("dmax", [1, 2, 3, 4, 5])
+def test_smaller_dmax(dmax):
+    rng = np.random.default_rng(dmax)
+    n = 3000
+    a = (rng.standard_normal((dmax + 1, n)) + 1j * rng.standard_normal((dmax + 1, n))) / np.sqrt(2)
+    deg = rng.integers(1, dmax + 1, n).astype(np.int32)
+    ref, ref_st = oracle.solve(a, deg)
+    for precision in ("fp64", "fp32_polish"):
+        got, st = _solve(a, deg, precision)
+        assert np.array_equal(st & 0x7, ref_st & 0x7)
+        _check_roots(got, st, a, deg, ref, ref_st, floor=1e-9, flagged_ok=precision != "fp64")
+
+
+def test_invalid_inputs_and_flags():
+    a = workloads.gaussian(8, seed=1)
+    deg = np.array([6, 0, 7, 6, 6, 1, -3, 6], dtype=np.int32)
+    a[2, 3] = np.nan
+    a[6, 4] = 0.0
+    a[1, 7] = np.inf
+    ref, ref_st = oracle.solve(a, deg)
+    for precision in ("fp64", "fp32_polish"):
+        got, st = _solve(a, deg, precision)
+        np.testing.assert_array_equal(st.astype(np.uint32) & 0x7, ref_st)
+        for i in (1, 2, 3, 4, 6, 7):
+            assert np.all(np.isnan(got[:, i]))
+        assert abs(got[0, 5] - ref[0, 5]) <= 4e-16 * abs(ref[0, 5])
+        assert np.all(np.isnan(got[1:, 5]))
+
+
+def test_special_polynomials():
+    cols = []
+    for d in range(2, 7):
+        z = np.zeros(7, dtype=np.complex128); z[d] = 1.0          # z^d
+        cols.append(z)
+        for c in (1.0, -1.0, 1j, 2.0):
+            w = np.zeros(7, dtype=np.complex128); w[0] = -c; w[d] = 1.0   # z^d - c
+            cols.append(w)
+    a = np.stack(cols, axis=1)
+    deg = np.array([int(np.nonzero(a[:, i])[0].max()) for i in range(a.shape[1])], dtype=np.int32)
+    ref, ref_st = oracle.solve(a, deg)
+    got, st = _solve(a, deg, "fp64")
+    assert np.all(st == 0) and np.all(ref_st == 0)
+    m = match_mixed(got, ref, deg)
+    v = valid_mask(6, deg, a.shape[1])
+    assert np.abs(m - ref)[v].max() < 1e-14 * 4
+    # with the exceptional shift off, z^d - c stalls and is flagged
+    got, st = _solve(a, deg, "fp64", flags=pr.FLAG_NO_EXCEPTIONAL_SHIFT)
+    _, ost = oracle.solve(a, deg, flags=oracle.FLAG_NO_EXCEPTIONAL_SHIFT)
+    np.testing.assert_array_equal(st.astype(np.uint32) & pr.ST_NOT_CONVERGED, ost & pr.ST_NOT_CONVERGED)
+    assert (st & pr.ST_NOT_CONVERGED).sum() > 0
+    # a cap of one step per level flags (nearly) everything, host-forced
+    g = workloads.gaussian(512, seed=2)
+    got, st = _solve(g, None, "fp64", max_iter_per_level=1)
+    assert ((st & pr.ST_NOT_CONVERGED) != 0).mean() > 0.9
+
+
+def test_non_monic():
+    a = workloads.gaussian(20000, seed=4) * (0.3 - 2.1j)
+    ref, _ = oracle.solve(a)
+    for precision in ("fp64", "fp32_polish"):
+        got, st = _solve(a, None, precision)
+        _check_roots(got, st, a, None, ref, np.zeros(a.shape[1], np.uint32),
+                     flagged_ok=precision != "fp64")
+
+
+def test_vieta_trace_on_gpu():
+    """Sum of the roots equals -a_5 (monic) up to rounding, converged or not."""
+    a = workloads.gaussian(65536, seed=7)
+    got, st = _solve(a, None, "fp64", max_iter_per_level=3)
+    s = got.sum(axis=0)
+    scale = np.abs(got).sum(axis=0)
+    assert np.all(np.abs(s + a[5]) <= 64 * 2.0 ** -53 * scale)
+
+
+def test_iteration_counts_distribution():
+    """Exact per-level counts depend on rounding (parity unpinned); their
+    distribution must match the oracle's, and z^d deflates in one step."""
+    a = workloads.gaussian(65536, seed=0)
+    _, _, oit = oracle.solve(a, return_iters=True)
+    got, st, it = _solve(a, None, "fp64", iter_counts=True)
+    assert it.shape == (5, 65536)
+    assert np.abs(it.mean(axis=1) - oit.mean(axis=1)).max() < 0.05 * oit.mean(axis=1).max()
+    assert (it == oit).mean() > 0.9
+    z = np.zeros((7, 4), dtype=np.complex128); z[6] = 1.0
+    _, _, zit = _solve(z, None, "fp64", iter_counts=True)
+    assert np.all(zit == 1)
+
+
+def test_deterministic():
+    a = workloads.gaussian(65536, seed=5)
+    for precision in ("fp64", "fp32_polish"):
+        r1, s1 = _solve(a, None, precision)
+        r2, s2 = _solve(a, None, precision)
+        assert np.array_equal(r1, r2, equal_nan=True) and np.array_equal(s1, s2)
+
+
+def test_stream_and_out_buffers():
+    a = workloads.gaussian(4096, seed=6)
+    ref, _ = oracle.solve(a)
+    s = torch.cuda.Stream()
+    ca = to_dev(a)
+    roots = torch.empty((6, 4096), dtype=torch.complex128, device=ca.device)
+    status = torch.empty((4096,), dtype=torch.int32, device=ca.device)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        pr.solve(ca, None, "fp64", roots=roots, status=status)
+    s.synchronize()
+    assert rel_err(match(to_host(roots), ref), ref).max() < 1e-10
