@@ -36,6 +36,27 @@ PEAK_FP32_NONPACKED = 78.6e12
 PEAK_HBM = 8.0e12            # B/s
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "solve_fp32_polish_parametric4096_traffic.json")
+
+
+def measured_traffic(form, grid):
+    """HBM bytes per launch of the solve kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record (calibrated against a copy kernel), or
+    None when that record does not describe the kernel as it is now (its
+    sources changed since the counters were taken) or this workload."""
+    import hashlib
+    if form != "fp32_polish" or grid != 4096 or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = json.load(open(TRAFFIC_RECORD))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def polish_flops(d, steps):
     return d * steps * (16 * d + 13)
 
@@ -82,6 +103,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", choices=["fp32_polish", "fp64"], default=None,
                     help="run only the timed steps of one form (for profilers)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="first stream MIB MiB through a plain elementwise kernel (read + write "
+                         "of known size) so that memory counters can be calibrated")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -94,6 +118,14 @@ def main():
     import paper_2507_02164_amd as pr
 
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        src = torch.ones(args.calib_copy * 2 ** 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written "
+            "by one elementwise kernel")
+        del src, dst
     g = args.grid
     n = g * g
     log(f"generating parametric grid {g}x{g} ({n} polynomials)")
@@ -181,7 +213,10 @@ def main():
                                "step = solve + density + backward",
                    "n_polys": n, "degree": 6, "image": [1920, 1080], "form": main_form},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(main_form, g),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "alg_bytes_per_launch": 212 * n,
                      "kernel": f"solve_{main_form}",
                      "flops_per_launch": r["alg_flops_per_poly"] * n,
                      "avg_launch_ms": r["solve_ms"]},
