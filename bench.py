@@ -66,6 +66,19 @@ def log(msg):
     sys.stderr.flush()
 
 
+def lockstep_flops(iters, wave=64):
+    """FLOPs the level-synchronous waves execute: per wave of 64 consecutive
+    polynomials and per level, the largest step count times F(m) times 64."""
+    it = iters.astype(np.float64)
+    n = it.shape[1]
+    nw = n // wave
+    tot = 0.0
+    for m in range(2, 7):
+        w = it[m - 2, :nw * wave].reshape(nw, wave).max(axis=1)
+        tot += w.sum() * F_LEVEL[m] * wave
+    return tot
+
+
 def algorithmic_flops(iters):
     """Sum over polynomials and levels of steps x F(m).  iters [5, n] int."""
     it = iters.astype(np.float64)
@@ -187,7 +200,9 @@ def main():
                          alg_flops_per_poly=flops / n,
                          mean_qr_steps=float(its_h.sum(axis=0).mean()),
                          flagged_frac=float((st_h != 0).mean()),
-                         alg_tflops=flops / (solve_ms * 1e-3) / 1e12)
+                         alg_tflops=flops / (solve_ms * 1e-3) / 1e12,
+                         lockstep_efficiency=algorithmic_flops(its_h) / lockstep_flops(its_h),
+                         executed_sweep_tflops=lockstep_flops(its_h) / (solve_ms * 1e-3) / 1e12)
         log(f"{form}: step {step_ms:.3f} ms, solve {solve_ms:.3f} ms, density {dens_ms:.3f} ms, "
             f"backward {back_ms:.3f} ms")
 

@@ -49,10 +49,12 @@ constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------- Givens
 // (c, s) = (conj a, conj b) / rho, rho = sqrt(|a|^2 + |b|^2): the only pair
-// for which the Sec. II-C rotation maps (a, b) to (rho, 0).  rho == 0 gives
-// the identity.  Branch-free (a branch here would split the fully unrolled
-// QR step into basic blocks and stretch register lifetimes across them); the
-// price is the range: |a|^2 + |b|^2 must not overflow (entries below about
+// for which the Sec. II-C rotation maps (a, b) to (rho, 0).  Computed
+// branch-free (a branch here would split the fully unrolled QR step into
+// basic blocks and stretch register lifetimes across them).  rho == 0 (a and
+// b both zero) is handled by the caller, which then applies the identity --
+// the two entries are already (rho, 0) = (0, 0).  The price of branch-free
+// code is the range: |a|^2 + |b|^2 must not overflow (entries below about
 // 1e154 in FP64, 1e19 in FP32), otherwise NaN propagates and the level ends
 // NOT_CONVERGED.
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
@@ -64,19 +66,6 @@ template <typename T>
 __device__ __forceinline__ T pick(bool p, T a, T b)
 {
     return p ? a : b;
-}
-
-template <typename T>
-__device__ __forceinline__ void givens(cx<T> a, cx<T> b, cx<T>& c, cx<T>& s, T& rho)
-{
-    const T n2 = a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im;
-    const T inv = rsqrt_t(n2);
-    const bool z = !(n2 > T(0));
-    const T r = n2 * inv;
-    const T cr = a.re * inv, ci = -a.im * inv, sr = b.re * inv, si = -b.im * inv;
-    rho = pick(z, T(0), r);
-    c = {pick(z, T(1), cr), pick(z, T(0), ci)};
-    s = {pick(z, T(0), sr), pick(z, T(0), si)};
 }
 
 // (x, y) <- (c x + s y, -conj(s) x + conj(c) y): rows r-1, r (Alg. 2 row loop).
@@ -120,14 +109,17 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
     cx<T> cprev, sprev;
 #pragma unroll
     for (int r = 1; r < M; ++r) {
-        cx<T> c, s;
-        T rho;
-        givens(h[r - 1][r - 1], h[r][r - 1], c, s, rho);
-        c = {pick(act, c.re, T(1)), pick(act, c.im, T(0))};
-        s = {pick(act, s.re, T(0)), pick(act, s.im, T(0))};
+        const cx<T> a = h[r - 1][r - 1], b = h[r][r - 1];
+        const T n2 = a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im;
+        const T inv = rsqrt_t(n2);
+        // a lane rotates only if it acts this trip and (a, b) != 0 (NaN
+        // fails n2 > 0 too); otherwise (c, s) = (1, 0) and both entries stay
+        const bool go = act && n2 > T(0);
+        const cx<T> c = {pick(go, a.re * inv, T(1)), pick(go, -a.im * inv, T(0))};
+        const cx<T> s = {pick(go, b.re * inv, T(0)), pick(go, -b.im * inv, T(0))};
         // the rotation maps (h[r-1][r-1], h[r][r-1]) to (rho, 0)
-        h[r - 1][r - 1] = {pick(act, rho, h[r - 1][r - 1].re), pick(act, T(0), h[r - 1][r - 1].im)};
-        h[r][r - 1] = {pick(act, T(0), h[r][r - 1].re), pick(act, T(0), h[r][r - 1].im)};
+        h[r - 1][r - 1] = {pick(go, n2 * inv, a.re), pick(go, T(0), a.im)};
+        h[r][r - 1] = {pick(go, T(0), b.re), pick(go, T(0), b.im)};
 #pragma unroll
         for (int j = r; j < M; ++j)
             rot_rows(h[r - 1][j], h[r][j], c, s);
