@@ -107,12 +107,45 @@ def cpu_baseline(coeffs_host, target_s=10.0):
     }, roots, n
 
 
+def bench_mixed(args, torch, workloads, pr, dev):
+    """Mixed degrees 2..6: one persistent degree-sorted launch against the
+    index-order launch, FP32 + polish, solve only."""
+    n = 64 * 2 ** 20
+    log(f"generating {n} mixed-degree polynomials")
+    a_host, deg_host = workloads.mixed(n, seed=0)
+    a = torch.from_numpy(a_host).to(dev)
+    deg = torch.from_numpy(deg_host).to(dev)
+    del a_host
+    roots = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    status = torch.empty((n,), dtype=torch.int32, device=dev)
+    out = {}
+    for form in ("fp32_polish", "fp64"):
+        for layout, tile in (("tiled", 0), ("flat", -1)):
+            for _ in range(args.warmup):
+                pr.solve(a, deg, form, roots=roots, status=status, tile=tile)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                pr.solve(a, deg, form, roots=roots, status=status, tile=tile)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            out[f"{form}_{layout}"] = {"solve_ms": ms, "polys_per_s": n / (ms * 1e-3)}
+            log(f"{form} {layout}: {ms:.3f} ms/solve, {n / (ms * 1e-3):.3e} polys/s")
+    print(json.dumps({"workload": "mixed degrees 2..6, 64Mi polynomials", "n": n, "results": out}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=4096, help="grid side; n = grid^2")
+    ap.add_argument("--workload", choices=["parametric", "mixed"], default="parametric",
+                    help="parametric: the default timed workload; mixed: 64M polynomials of "
+                         "degrees 2..6 (solve only, both launch layouts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", choices=["fp32_polish", "fp64"], default=None,
                     help="run only the timed steps of one form (for profilers)")
@@ -139,6 +172,8 @@ def main():
         log(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written "
             "by one elementwise kernel")
         del src, dst
+    if args.workload == "mixed":
+        return bench_mixed(args, torch, workloads, pr, dev)
     g = args.grid
     n = g * g
     log(f"generating parametric grid {g}x{g} ({n} polynomials)")

@@ -91,6 +91,13 @@ typedef struct pr_solve_opts {
                                      exceeds polish_tol * |r|; 0 = 1e-6; valid (0, 1) */
     int32_t* iter_counts;         /* optional DEVICE array [dmax-1][n] (row m-2 = QR steps
                                      taken at level m), or NULL */
+    int32_t tile;                 /* with a degrees array: polynomials are solved in tiles of
+                                     this many consecutive indices, each sorted by degree so
+                                     that every wave holds one degree (one persistent launch);
+                                     0 = library default (2048), -1 = no sorting (index order);
+                                     valid -1..4096 */
+    int32_t grid_blocks;          /* tiled launch: number of one-wave blocks that walk the
+                                     tiles (0 = 8 per compute unit); valid >= 0 */
 } pr_solve_opts;
 
 /*

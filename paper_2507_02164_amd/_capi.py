@@ -48,6 +48,8 @@ class SolveOpts(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("polish_tol", ctypes.c_double),
         ("iter_counts", ctypes.c_void_p),
+        ("tile", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
     ]
 
 
@@ -109,7 +111,8 @@ def _ptr(t):
 
 
 def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=0, polish_steps=0,
-          polish_tol=0.0, flags=0, iter_counts=False, roots=None, status=None, stream=None):
+          polish_tol=0.0, flags=0, iter_counts=False, roots=None, status=None, stream=None,
+          tile=0, grid_blocks=0):
     """Roots of each column of ``coeffs`` (complex128 [dmax+1, n], row k =
     a_k).  Returns ``(roots complex128 [dmax, n], status int32 [n])``, plus
     the per-level QR step counts int32 [dmax-1, n] when ``iter_counts``.
@@ -133,7 +136,7 @@ def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=0, polis
         its = torch.empty((max(dmax - 1, 0), n), dtype=torch.int32, device=dev)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = SolveOpts(prec, max_iter_per_level, polish_steps, flags, polish_tol,
-                     None if its is None or its.numel() == 0 else its.data_ptr())
+                     None if its is None or its.numel() == 0 else its.data_ptr(), tile, grid_blocks)
     with torch.cuda.device(dev):
         rc = lib().pr_solve(_ptr(coeffs), _ptr(degrees), n, dmax, _ptr(roots), _ptr(status),
                             ctypes.byref(opts), _stream(stream))

@@ -15,8 +15,28 @@ namespace {
 constexpr int kDefaultCap = 30;
 constexpr int kDefaultPolishSteps = 2;
 constexpr double kDefaultPolishTol = 1e-6;
+constexpr int kDefaultTile = 2048;
+constexpr int kDefaultBlocksPerCU = 8;
+constexpr int kMaxDevices = 64;
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? PR_OK : PR_ERR_HIP; }
+
+// Compute-unit count of the current device, looked up once per device.
+int cu_count()
+{
+    static int cached[kMaxDevices] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
 
 }  // namespace
 
@@ -41,6 +61,8 @@ extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_
         return PR_ERR_INVALID_ARG;
     if (o.flags & ~(uint32_t)PR_FLAG_NO_EXCEPTIONAL_SHIFT)
         return PR_ERR_UNSUPPORTED;
+    if (o.tile < -1 || o.tile > max_tile() || o.grid_blocks < 0)
+        return PR_ERR_INVALID_ARG;
     if (n == 0)
         return PR_OK;
     if (n > (int64_t)0x7fffffff * 256)
@@ -57,6 +79,10 @@ extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_
     a.flags = o.flags;
     a.polish_steps = o.polish_steps ? o.polish_steps : kDefaultPolishSteps;
     a.polish_tol = o.polish_tol > 0.0 ? o.polish_tol : kDefaultPolishTol;
+    a.tile = o.tile == 0 ? kDefaultTile : (o.tile < 0 ? 0 : o.tile);
+    a.grid_blocks = 0;
+    if (degrees && a.tile > 0)
+        a.grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : kDefaultBlocksPerCU * cu_count();
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (o.precision == PR_FP64)
         return hip_status(launch_solve_fp64(a, s));

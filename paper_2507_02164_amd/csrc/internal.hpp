@@ -21,8 +21,11 @@ struct SolveArgs {
     uint32_t flags;
     int32_t polish_steps;
     double polish_tol;
+    int32_t tile;         // > 0 with degrees: persistent degree-bucketed launch
+    int32_t grid_blocks;  // persistent launch: number of one-wave blocks (0 = one per tile)
 };
 
+int max_tile();
 hipError_t launch_solve_fp64(const SolveArgs& a, hipStream_t stream);
 hipError_t launch_solve_fp32_polish(const SolveArgs& a, hipStream_t stream);
 

@@ -39,6 +39,8 @@
 //     coefficients.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cplx.hpp"
 #include "internal.hpp"
 
@@ -239,15 +241,6 @@ __device__ __forceinline__ void companion(cx<T> (&h)[DM][DM], int d,
         h[i][i - 1] = {i < d ? T(1) : T(0), T(0)};
 }
 
-template <int DM>
-__device__ __forceinline__ void zero_iters(int32_t* iters, int64_t n, int64_t i)
-{
-    if (iters)
-#pragma unroll
-        for (int m = 2; m <= DM; ++m)
-            iters[(int64_t)(m - 2) * n + i] = 0;
-}
-
 // Load a_0..a_d (zeros above d), validate, and normalise to b = a / a_d.
 template <int DM>
 __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs, int64_t n,
@@ -273,71 +266,8 @@ __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs
     const bool monic = lead.re == 1.0 && lead.im == 0.0;
 #pragma unroll
     for (int k = 0; k <= DM; ++k)
-        b[k] = (k < d && !monic) ? cdiv(a[k], lead) : a[k];
+        b[k] = (k < d && !monic && !st) ? cdiv(a[k], lead) : a[k];
     return st;
-}
-
-#ifndef PR_FP64_WAVES
-#define PR_FP64_WAVES 1
-#endif
-#ifndef PR_FP32_WAVES
-#define PR_FP32_WAVES 1
-#endif
-
-template <int DM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PR_FP64_WAVES))) void solve_fp64_kernel(
-    const double2* __restrict__ coeffs, const int32_t* __restrict__ degrees, int64_t n,
-    double2* __restrict__ roots, uint32_t* __restrict__ status, int32_t* __restrict__ iters,
-    int cap, uint32_t flags)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n)
-        return;
-    const int d = degrees ? degrees[i] : DM;
-    const double qnan = __builtin_nan("");
-#pragma unroll
-    for (int k = 0; k < DM; ++k)
-        if (k >= d)
-            roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
-    if (d < 1 || d > DM) {
-        status[i] = PR_ST_BAD_DEGREE;
-#pragma unroll
-        for (int k = 0; k < DM; ++k)
-            if (k < d)
-                roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
-        zero_iters<DM>(iters, n, i);
-        return;
-    }
-    cx<double> a[DM + 1], b[DM + 1];
-    uint32_t st = load_poly<DM>(coeffs, n, i, d, a, b);
-    if (st) {
-#pragma unroll
-        for (int k = 0; k < DM; ++k)
-            if (k < d)
-                roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
-        status[i] = st;
-        zero_iters<DM>(iters, n, i);
-        return;
-    }
-    cx<double> h[DM][DM];
-#pragma unroll
-    for (int r = 0; r < DM; ++r)
-#pragma unroll
-        for (int c = (r > 0 ? r - 1 : 0); c < DM; ++c)
-            h[r][c] = {0.0, 0.0};
-    companion<double, DM>(h, d, b);
-    if (iters)
-#pragma unroll
-        for (int m = 2; m <= DM; ++m)
-            if (m > d)
-                iters[(int64_t)(m - 2) * n + i] = 0;
-
-    const bool exc = !(flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT);
-    iterate<double, DM>(h, d, cap, exc, st, iters, n, i, [&](int k, cx<double> v) {
-        roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
-    });
-    roots[i] = make_double2(h[0][0].re, h[0][0].im);
-    status[i] = st;
 }
 
 // Newton polish in FP64 on the original coefficients a (zeros above the
@@ -367,152 +297,280 @@ __device__ __forceinline__ cx<double> polish(cx<double> r, const cx<double> (&a)
     return r;
 }
 
-template <int DM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PR_FP32_WAVES))) void solve_fp32_polish_kernel(
-    const double2* __restrict__ coeffs, const int32_t* __restrict__ degrees, int64_t n,
-    double2* __restrict__ roots, uint32_t* __restrict__ status, int32_t* __restrict__ iters,
-    int cap, uint32_t flags, int polish_steps, double polish_tol,
-    const double2* coeffs_again)
+// Everything a lane needs to solve one polynomial.
+struct PolyIO {
+    const double2* coeffs;
+    const double2* coeffs_again;  // same array, second pointer: the FP32 form re-reads it
+    const int32_t* degrees;
+    int64_t n;
+    double2* roots;
+    uint32_t* status;
+    int32_t* iters;
+    int cap;
+    uint32_t flags;
+    int polish_steps;
+    double polish_tol;
+};
+
+// Solve polynomial i on this lane.  valid == false: the lane has no
+// polynomial this round and only rides along in the wave's level loops.
+// FP32 selects the FP32-sweep + FP64-polish form.  No early return: every
+// lane of the wave reaches the wave-uniform loops.
+template <bool FP32, int DM>
+__device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool valid)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n)
-        return;
-    const int d = degrees ? degrees[i] : DM;
+    using T = typename std::conditional<FP32, float, double>::type;
+    const int64_t n = io.n;
     const double qnan = __builtin_nan("");
-    if (d < 1 || d > DM) {
-#pragma unroll
-        for (int k = 0; k < DM; ++k)
-            roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
-        status[i] = PR_ST_BAD_DEGREE;
-        zero_iters<DM>(iters, n, i);
-        return;
-    }
+    int d = valid ? (io.degrees ? io.degrees[i] : DM) : 0;
+    uint32_t st = 0;
+    if (valid && (d < 1 || d > DM))
+        st = PR_ST_BAD_DEGREE;
     cx<double> a[DM + 1], b[DM + 1];
-    uint32_t st = load_poly<DM>(coeffs, n, i, d, a, b);
-    if (st) {
+#pragma unroll
+    for (int k = 0; k <= DM; ++k)
+        a[k] = b[k] = {0.0, 0.0};
+    if (valid && !st)
+        st = load_poly<DM>(io.coeffs, n, i, d, a, b);
+    const bool ok = valid && !st;
+    const int dd = ok ? d : 0;  // 0: this lane takes no level
+    if (valid) {
 #pragma unroll
         for (int k = 0; k < DM; ++k)
-            roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
-        status[i] = st;
-        zero_iters<DM>(iters, n, i);
-        return;
+            if (k >= dd)
+                io.roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
+        if (io.iters)
+#pragma unroll
+            for (int m = 2; m <= DM; ++m)
+                if (m > dd)
+                    io.iters[(int64_t)(m - 2) * n + i] = 0;
     }
-    cx<float> h[DM][DM];
+    cx<T> h[DM][DM];
 #pragma unroll
     for (int r = 0; r < DM; ++r)
 #pragma unroll
         for (int c = (r > 0 ? r - 1 : 0); c < DM; ++c)
-            h[r][c] = {0.0f, 0.0f};
-    companion<float, DM>(h, d, b);
-    if (iters)
-#pragma unroll
-        for (int m = 2; m <= DM; ++m)
-            if (m > d)
-                iters[(int64_t)(m - 2) * n + i] = 0;
+            h[r][c] = {T(0), T(0)};
+    companion<T, DM>(h, dd, b);
+    const bool exc = !(io.flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT);
 
-    cx<float> e[DM];
+    if constexpr (!FP32) {
+        iterate<double, DM>(h, dd, io.cap, exc, st, io.iters, n, i, [&](int k, cx<double> v) {
+            io.roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
+        });
+        if (ok)
+            io.roots[i] = make_double2(h[0][0].re, h[0][0].im);
+    } else {
+        cx<float> e[DM];
 #pragma unroll
-    for (int k = 0; k < DM; ++k)
-        e[k] = {0.0f, 0.0f};
-    const bool exc = !(flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT);
-    iterate<float, DM>(h, d, cap, exc, st, iters, n, i, [&](int k, cx<float> v) {
-        // k is a compile-time constant after inlining
+        for (int k = 0; k < DM; ++k)
+            e[k] = {0.0f, 0.0f};
+        iterate<float, DM>(h, dd, io.cap, exc, st, io.iters, n, i, [&](int k, cx<float> v) {
+            // k is a compile-time constant after inlining
 #pragma unroll
-        for (int q = 0; q < DM; ++q)
-            if (q == k)
-                e[q] = v;
-    });
-    e[0] = h[0][0];
-
-    // The original coefficients, read again (through a second pointer, so
-    // the compiler cannot keep the first load alive across the QR loop).
+            for (int q = 0; q < DM; ++q)
+                if (q == k)
+                    e[q] = v;
+        });
+        e[0] = h[0][0];
+        if (ok) {
+            // The original coefficients, read again (through a second
+            // pointer, so the compiler cannot keep the first load alive
+            // across the QR loop).
 #pragma unroll
-    for (int k = 0; k <= DM; ++k) {
-        a[k] = {0.0, 0.0};
-        if (k <= d) {
-            const double2 v = coeffs_again[(int64_t)k * n + i];
-            a[k] = {v.x, v.y};
-        }
-    }
-    cx<double> r[DM];
-    const double tol2 = polish_tol * polish_tol;
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < DM; ++k) {
-        r[k] = {qnan, qnan};
-        if (k < d) {
-            double last2;
-            r[k] = polish<DM>(cx<double>{(double)e[k].re, (double)e[k].im}, a, polish_steps, last2);
-            if (!(last2 <= tol2 * norm2(r[k])))
-                bad = true;
-        }
-    }
-    // Two polished roots on top of each other: one root was lost.
-#pragma unroll
-    for (int j = 0; j < DM; ++j)
-#pragma unroll
-        for (int k = j + 1; k < DM; ++k)
-            if (k < d) {
-                double sep2 = norm2(r[j] - r[k]);
-                double mag = fmax(norm2(r[j]), 1.0) * 1e-16;  // (1e-8 max(|r_j|, 1))^2
-                if (sep2 <= mag)
-                    bad = true;
+            for (int k = 0; k <= DM; ++k) {
+                a[k] = {0.0, 0.0};
+                if (k <= d) {
+                    const double2 v = io.coeffs_again[(int64_t)k * n + i];
+                    a[k] = {v.x, v.y};
+                }
             }
-    if (bad)
-        st |= PR_ST_POLISH_UNCONVERGED;
+            cx<double> r[DM];
+            const double tol2 = io.polish_tol * io.polish_tol;
+            bool bad = false;
 #pragma unroll
-    for (int k = 0; k < DM; ++k)
-        roots[(int64_t)k * n + i] = make_double2(r[k].re, r[k].im);
-    status[i] = st;
+            for (int k = 0; k < DM; ++k) {
+                r[k] = {qnan, qnan};
+                if (k < d) {
+                    double last2;
+                    r[k] = polish<DM>(cx<double>{(double)e[k].re, (double)e[k].im}, a,
+                                      io.polish_steps, last2);
+                    if (!(last2 <= tol2 * norm2(r[k])))
+                        bad = true;
+                }
+            }
+            // Two polished roots on top of each other: one root was lost.
+#pragma unroll
+            for (int j = 0; j < DM; ++j)
+#pragma unroll
+                for (int k = j + 1; k < DM; ++k)
+                    if (k < d) {
+                        double sep2 = norm2(r[j] - r[k]);
+                        double mag = fmax(norm2(r[j]), 1.0) * 1e-16;  // (1e-8 max(|r_j|, 1))^2
+                        if (sep2 <= mag)
+                            bad = true;
+                    }
+            if (bad)
+                st |= PR_ST_POLISH_UNCONVERGED;
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                if (k < d)
+                    io.roots[(int64_t)k * n + i] = make_double2(r[k].re, r[k].im);
+        }
+    }
+    if (valid)
+        io.status[i] = st;
 }
 
-template <int DM>
-hipError_t launch_fp64_dm(const SolveArgs& a, hipStream_t stream)
+#ifndef PR_FP64_WAVES
+#define PR_FP64_WAVES 1
+#endif
+#ifndef PR_FP32_WAVES
+#define PR_FP32_WAVES 1
+#endif
+template <bool FP32>
+struct WavesPerEU {
+    static constexpr int v = FP32 ? PR_FP32_WAVES : PR_FP64_WAVES;
+};
+
+// One lane per polynomial in index order (all polynomials of one degree, or
+// no degree array).
+template <bool FP32, int DM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32>::v)))
+void solve_flat_kernel(PolyIO io)
 {
-    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(solve_fp64_kernel<DM>, dim3((unsigned)blocks), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const double2*>(a.coeffs), a.degrees, a.n,
-                       reinterpret_cast<double2*>(a.roots), a.status, a.iters, a.cap, a.flags);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    solve_poly<FP32, DM>(io, i, i < io.n);
+}
+
+// Mixed degrees, one persistent launch.  Each block is one wave and walks
+// tiles of `tile` consecutive polynomials (grid-stride, no work counter to
+// reset).  Per tile it counting-sorts the polynomials by degree with
+// ballots (deterministic order, no atomics) into an LDS index list in which
+// every degree bucket is padded to a multiple of 64, then solves the list 64
+// entries at a time: each slice holds one degree, so no lane idles through
+// levels above its degree.  The gathers stay inside the tile, which the
+// caches hold.
+constexpr int kTileMax = 4096;
+constexpr int kWave = 64;
+
+template <bool FP32, int DM>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32>::v)))
+void solve_tiled_kernel(PolyIO io, int tile)
+{
+    __shared__ uint16_t list[kTileMax + (DM + 1) * kWave];
+    const int lane = threadIdx.x;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this lane
+    for (int64_t base = (int64_t)blockIdx.x * tile; base < io.n;
+         base += (int64_t)gridDim.x * tile) {
+        const int cnt_t = (int)((io.n - base) < tile ? (io.n - base) : tile);
+        // pass 1: bucket sizes (bucket 0 = invalid degree)
+        int count[DM + 1];
+#pragma unroll
+        for (int b = 0; b <= DM; ++b)
+            count[b] = 0;
+        for (int t0 = 0; t0 < cnt_t; t0 += kWave) {
+            const int t = t0 + lane;
+            int bk = -1;
+            if (t < cnt_t) {
+                const int d = io.degrees[base + t];
+                bk = (d >= 1 && d <= DM) ? d : 0;
+            }
+#pragma unroll
+            for (int b = 0; b <= DM; ++b)
+                count[b] += __builtin_popcountll(__ballot(bk == b));
+        }
+        int start[DM + 1];
+        int total = 0;
+#pragma unroll
+        for (int b = 0; b <= DM; ++b) {
+            start[b] = total;
+            total += (count[b] + kWave - 1) / kWave * kWave;
+        }
+        for (int t = lane; t < total; t += kWave)
+            list[t] = 0xFFFF;
+        __syncthreads();
+        // pass 2: scatter tile-local indices into their buckets
+        for (int t0 = 0; t0 < cnt_t; t0 += kWave) {
+            const int t = t0 + lane;
+            int bk = -1;
+            if (t < cnt_t) {
+                const int d = io.degrees[base + t];
+                bk = (d >= 1 && d <= DM) ? d : 0;
+            }
+#pragma unroll
+            for (int b = 0; b <= DM; ++b) {
+                const uint64_t m = __ballot(bk == b);
+                if (bk == b)
+                    list[start[b] + __builtin_popcountll(m & below)] = (uint16_t)t;
+                start[b] += __builtin_popcountll(m);
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < total; s += kWave) {
+            const uint16_t e = list[s + lane];
+            const bool valid = e != 0xFFFF;
+            solve_poly<FP32, DM>(io, base + (valid ? e : 0), valid);
+        }
+        __syncthreads();
+    }
+}
+
+template <bool FP32, int DM>
+hipError_t launch_dm(const SolveArgs& a, hipStream_t stream)
+{
+    PolyIO io;
+    io.coeffs = reinterpret_cast<const double2*>(a.coeffs);
+    io.coeffs_again = io.coeffs;
+    io.degrees = a.degrees;
+    io.n = a.n;
+    io.roots = reinterpret_cast<double2*>(a.roots);
+    io.status = a.status;
+    io.iters = a.iters;
+    io.cap = a.cap;
+    io.flags = a.flags;
+    io.polish_steps = a.polish_steps;
+    io.polish_tol = a.polish_tol;
+    if (a.degrees && a.tile > 0) {
+        const int tile = a.tile;
+        const int64_t tiles = (a.n + tile - 1) / tile;
+        const int64_t grid = a.grid_blocks > 0 && a.grid_blocks < tiles ? a.grid_blocks : tiles;
+        hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM>), dim3((unsigned)grid), dim3(kWave), 0,
+                           stream, io, tile);
+    } else {
+        const int64_t blocks = (a.n + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((solve_flat_kernel<FP32, DM>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                           stream, io);
+    }
     return hipGetLastError();
 }
 
-template <int DM>
-hipError_t launch_fp32_dm(const SolveArgs& a, hipStream_t stream)
+template <bool FP32>
+hipError_t launch_form(const SolveArgs& a, hipStream_t stream)
 {
-    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(solve_fp32_polish_kernel<DM>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                       stream, reinterpret_cast<const double2*>(a.coeffs), a.degrees, a.n,
-                       reinterpret_cast<double2*>(a.roots), a.status, a.iters, a.cap, a.flags,
-                       a.polish_steps, a.polish_tol, reinterpret_cast<const double2*>(a.coeffs));
-    return hipGetLastError();
+    switch (a.dmax) {
+    case 1: return launch_dm<FP32, 1>(a, stream);
+    case 2: return launch_dm<FP32, 2>(a, stream);
+    case 3: return launch_dm<FP32, 3>(a, stream);
+    case 4: return launch_dm<FP32, 4>(a, stream);
+    case 5: return launch_dm<FP32, 5>(a, stream);
+    case 6: return launch_dm<FP32, 6>(a, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_solve_fp64(const SolveArgs& a, hipStream_t stream)
 {
-    switch (a.dmax) {
-    case 1: return launch_fp64_dm<1>(a, stream);
-    case 2: return launch_fp64_dm<2>(a, stream);
-    case 3: return launch_fp64_dm<3>(a, stream);
-    case 4: return launch_fp64_dm<4>(a, stream);
-    case 5: return launch_fp64_dm<5>(a, stream);
-    case 6: return launch_fp64_dm<6>(a, stream);
-    }
-    return hipErrorInvalidValue;
+    return launch_form<false>(a, stream);
 }
 
 hipError_t launch_solve_fp32_polish(const SolveArgs& a, hipStream_t stream)
 {
-    switch (a.dmax) {
-    case 1: return launch_fp32_dm<1>(a, stream);
-    case 2: return launch_fp32_dm<2>(a, stream);
-    case 3: return launch_fp32_dm<3>(a, stream);
-    case 4: return launch_fp32_dm<4>(a, stream);
-    case 5: return launch_fp32_dm<5>(a, stream);
-    case 6: return launch_fp32_dm<6>(a, stream);
-    }
-    return hipErrorInvalidValue;
+    return launch_form<true>(a, stream);
 }
+
+int max_tile() { return kTileMax; }
 
 }  // namespace proots

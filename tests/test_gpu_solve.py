@@ -242,3 +242,29 @@ def test_stream_and_out_buffers():
         pr.solve(ca, None, "fp64", roots=roots, status=status)
     s.synchronize()
     assert rel_err(match(to_host(roots), ref), ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
+def test_tiled_equals_flat(precision):
+    """Degree-sorted tiles only regroup the lanes: every lane's arithmetic is
+    its own, so roots, status and step counts are bit-identical to the
+    index-order launch, for any tile size and grid."""
+    a, deg = workloads.mixed(30000, seed=8)
+    deg = deg.copy()
+    deg[::997] = 0          # invalid degrees mixed in
+    deg[5::1009] = 7
+    flat = _solve(a, deg, precision, tile=-1, iter_counts=True)
+    for tile, grid in [(64, 0), (100, 3), (2048, 0), (4096, 1), (1000, 7), (2048, 100000)]:
+        got = _solve(a, deg, precision, tile=tile, grid_blocks=grid, iter_counts=True)
+        for x, y in zip(got, flat):
+            assert np.array_equal(x, y, equal_nan=True), (tile, grid)
+    ref, ref_st = oracle.solve(a, deg)
+    np.testing.assert_array_equal(flat[1].astype(np.uint32) & 0x7, ref_st & 0x7)
+
+
+def test_tile_argument_validation():
+    a = to_dev(workloads.gaussian(16, seed=0))
+    d = to_dev(np.full(16, 6, dtype=np.int32))
+    for bad in (dict(tile=-2), dict(tile=4097), dict(grid_blocks=-1)):
+        with pytest.raises(pr.ProotsError):
+            pr.solve(a, d, "fp64", **bad)
