@@ -120,7 +120,7 @@ def bench_mixed(args, torch, workloads, pr, dev):
     status = torch.empty((n,), dtype=torch.int32, device=dev)
     out = {}
     for form in ("fp32_polish", "fp64"):
-        for layout, tile in (("tiled", 0), ("flat", -1)):
+        for layout, tile in (("tiled", None), ("flat", -1)):
             for _ in range(args.warmup):
                 pr.solve(a, deg, form, roots=roots, status=status, tile=tile)
             torch.cuda.synchronize()

@@ -110,13 +110,15 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=0, polish_steps=0,
+def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=None, polish_steps=0,
           polish_tol=0.0, flags=0, iter_counts=False, roots=None, status=None, stream=None,
-          tile=0, grid_blocks=0):
+          tile=None, grid_blocks=None):
     """Roots of each column of ``coeffs`` (complex128 [dmax+1, n], row k =
     a_k).  Returns ``(roots complex128 [dmax, n], status int32 [n])``, plus
     the per-level QR step counts int32 [dmax-1, n] when ``iter_counts``.
-    Status bits are the ST_* constants (the int32 holds the uint32 bits)."""
+    Status bits are the ST_* constants (the int32 holds the uint32 bits).
+    Launch layout and iteration cap left as None come from the autotuner's
+    cache for this GPU (library defaults when nothing was tuned)."""
     _check(coeffs, "coeffs", torch.complex128)
     if coeffs.dim() != 2:
         raise ValueError("coeffs must be 2-D [dmax+1, n]")
@@ -135,6 +137,16 @@ def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=0, polis
     if iter_counts:
         its = torch.empty((max(dmax - 1, 0), n), dtype=torch.int32, device=dev)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if max_iter_per_level is None or tile is None or grid_blocks is None:
+        from . import autotune
+        name = {v: k for k, v in PRECISIONS.items()}.get(prec, str(prec))
+        tuned = autotune.tuned_options(name, dmax, degrees is not None, dev)
+        if max_iter_per_level is None:
+            max_iter_per_level = tuned.get("max_iter_per_level", 0)
+        if tile is None:
+            tile = tuned.get("tile", 0)
+        if grid_blocks is None:
+            grid_blocks = tuned.get("grid_blocks", 0)
     opts = SolveOpts(prec, max_iter_per_level, polish_steps, flags, polish_tol,
                      None if its is None or its.numel() == 0 else its.data_ptr(), tile, grid_blocks)
     with torch.cuda.device(dev):

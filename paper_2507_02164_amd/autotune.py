@@ -1,0 +1,162 @@
+"""Launch-layout autotuner for pr_solve.
+
+For a sample of the caller's workload it times every candidate layout on
+the GPU (HIP events, median of repeats) and keeps the fastest:
+
+  * tile         -- polynomials per degree-sorted tile (mixed degrees only),
+  * grid_blocks  -- one-wave blocks of the persistent launch, per compute unit,
+  * cap          -- QR steps per level before NOT_CONVERGED; a cap is only
+                    eligible if it flags no polynomial of the sample that the
+                    default cap of 30 does not flag.
+
+Results go to a JSON cache keyed by architecture, form, dmax and degree mix
+(``PROOTS_TUNE_CACHE`` overrides the path).  ``tuned_options`` reads it;
+``paper_2507_02164_amd.solve`` consults it when the caller leaves the layout
+options unset.
+
+    python -m paper_2507_02164_amd.autotune     # tunes the standard workloads
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from . import _capi
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(_HERE, "tuning", "tune_cache.json")
+
+TILES = (512, 1024, 2048, 4096)
+BLOCKS_PER_CU = (8, 16, 32, 64)
+CAPS = (20, 24, 30)
+
+_cache = None
+
+
+def cache_path() -> str:
+    return os.environ.get("PROOTS_TUNE_CACHE", DEFAULT_CACHE)
+
+
+_arch = {}
+
+
+def arch_name(device=None) -> str:
+    idx = torch.device(device).index if device is not None else 0
+    idx = 0 if idx is None else idx
+    if idx not in _arch:
+        props = torch.cuda.get_device_properties(idx)
+        _arch[idx] = getattr(props, "gcnArchName", "unknown").split(":")[0]
+    return _arch[idx]
+
+
+def key(arch, precision, dmax, mixed) -> str:
+    return f"{arch}/{precision}/dmax{dmax}/{'mixed' if mixed else 'uniform'}"
+
+
+def load_cache() -> dict:
+    global _cache
+    if _cache is None:
+        p = cache_path()
+        _cache = json.load(open(p)) if os.path.exists(p) else {}
+    return _cache
+
+
+def tuned_options(precision, dmax, mixed, device=None) -> dict:
+    """Options recorded for this configuration ({} when none were tuned)."""
+    if not torch.cuda.is_available():
+        return {}
+    c = load_cache()
+    return dict(c.get(key(arch_name(device), precision, dmax, mixed), {}).get("options", {}))
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> dict:
+    """Time the candidate layouts on this sample; returns the record
+    {"options": {...}, "ms": best, "trials": [...]}."""
+    dmax = coeffs.shape[0] - 1
+    n = coeffs.shape[1]
+    dev = coeffs.device
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    roots = torch.empty((dmax, n), dtype=torch.complex128, device=dev)
+    status = torch.empty((n,), dtype=torch.int32, device=dev)
+
+    def run(**o):
+        _capi.solve(coeffs, degrees, precision, roots=roots, status=status, **o)
+
+    # caps that flag nothing extra
+    run(max_iter_per_level=30, tile=-1)
+    torch.cuda.synchronize()
+    base_flags = int(((status & _capi.ST_NOT_CONVERGED) != 0).sum())
+    caps = []
+    for cap in CAPS:
+        run(max_iter_per_level=cap, tile=-1)
+        torch.cuda.synchronize()
+        if int(((status & _capi.ST_NOT_CONVERGED) != 0).sum()) <= base_flags:
+            caps.append(cap)
+    layouts = [dict(tile=-1)]
+    if degrees is not None:
+        layouts += [dict(tile=t, grid_blocks=b * cus) for t in TILES for b in BLOCKS_PER_CU]
+    trials = []
+    for cap in caps:
+        for lay in layouts:
+            o = dict(lay, max_iter_per_level=cap)
+            ms = _time(lambda: run(**o), reps)
+            trials.append({"options": o, "ms": ms})
+            log(f"  {precision} {o}: {ms:.3f} ms")
+    best = min(trials, key=lambda t: t["ms"])
+    return {"options": best["options"], "ms": best["ms"], "n": n, "trials": trials,
+            "eligible_caps": caps, "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def save(k, record):
+    c = load_cache()
+    c[k] = record
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def main():
+    import sys
+    root = os.path.dirname(_HERE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import workloads
+    dev = torch.device("cuda:0")
+    arch = arch_name(dev)
+    samples = {
+        False: (torch.from_numpy(workloads.parametric(2048, seed=0)).to(dev), None),
+    }
+    a, d = workloads.mixed(8 * 2 ** 20, seed=0)
+    samples[True] = (torch.from_numpy(a).to(dev), torch.from_numpy(d).to(dev))
+    for mixed, (c, deg) in samples.items():
+        for precision in ("fp32_polish", "fp64"):
+            print(f"tuning {precision} {'mixed' if mixed else 'uniform'} on n={c.shape[1]}", flush=True)
+            rec = tune(c, deg, precision)
+            save(key(arch, precision, c.shape[0] - 1, mixed), rec)
+            print(f"  -> {rec['options']} {rec['ms']:.3f} ms", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,3 +138,28 @@ def test_oracle_and_product_share_no_code():
         if f.endswith((".py", ".c", ".h")):
             txt = open(f).read()
             assert "paper_2507_02164_amd" not in txt and "proots.h" not in txt, f
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    """Cache keys and lookups (no GPU: only the JSON side)."""
+    from paper_2507_02164_amd import autotune
+    monkeypatch.setenv("PROOTS_TUNE_CACHE", str(tmp_path / "c.json"))
+    monkeypatch.setattr(autotune, "_cache", None)
+    k = autotune.key("gfx950", "fp32_polish", 6, True)
+    assert k == "gfx950/fp32_polish/dmax6/mixed"
+    autotune.save(k, {"options": {"tile": 1024, "grid_blocks": 2048, "max_iter_per_level": 30}})
+    monkeypatch.setattr(autotune, "_cache", None)
+    assert autotune.load_cache()[k]["options"]["tile"] == 1024
+
+
+def test_committed_tuning_cache_is_valid():
+    import json
+    from paper_2507_02164_amd import autotune
+    if not os.path.exists(autotune.DEFAULT_CACHE):
+        pytest.skip("no tuning cache committed yet")
+    c = json.load(open(autotune.DEFAULT_CACHE))
+    for k, rec in c.items():
+        o = rec["options"]
+        assert -1 <= o.get("tile", 0) <= 4096
+        assert o.get("grid_blocks", 0) >= 0
+        assert 1 <= o.get("max_iter_per_level", 30) <= 1000

@@ -123,8 +123,8 @@ def test_clustered_full_classes_and_image():
     _say("generating 16M clustered polynomials")
     coeffs, roots_true = workloads.clustered(n, seed=0)
     c = to_dev(coeffs)
-    r64, s64 = pr.solve(c, None, "fp64")
-    r32, s32 = pr.solve(c, None, "fp32_polish")
+    r64, s64 = pr.solve(c, None, "fp64", max_iter_per_level=30)
+    r32, s32 = pr.solve(c, None, "fp32_polish", max_iter_per_level=30)
     torch.cuda.synchronize()
     s64h, s32h = to_host(s64), to_host(s32)
     # Triple clusters converge linearly; with 30 steps per level about 0.07%

@@ -24,6 +24,7 @@ pr = pytest.importorskip("paper_2507_02164_amd")
 
 
 def _solve(a, deg=None, precision="fp64", **kw):
+    kw.setdefault("max_iter_per_level", 30)   # the oracle's cap
     out = pr.solve(to_dev(a), None if deg is None else to_dev(deg), precision, **kw)
     torch.cuda.synchronize()
     return tuple(to_host(t) for t in out)
