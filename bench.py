@@ -278,6 +278,30 @@ def main():
     if main_form == "fp32_polish":
         out["roofline"]["peak_nonpacked"] = PEAK_FP32_NONPACKED / 1e12
         out["roofline"]["frac_nonpacked"] = achieved / PEAK_FP32_NONPACKED
+    if args.profile_only is None:
+        # paper-literal mode (Alg. 2): exactly T = 10 QR steps per level, FP32
+        # sweeps as in the paper's implementations; reported as context
+        T = 10
+        for _ in range(args.warmup):
+            pr.solve(a, None, "fp32_polish", roots=roots, status=status, max_iter_per_level=T,
+                     flags=pr.FLAG_FIXED_STEPS)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            pr.solve(a, None, "fp32_polish", roots=roots, status=status, max_iter_per_level=T,
+                     flags=pr.FLAG_FIXED_STEPS)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out["paper_literal_fixed_T10"] = {
+            "solve_ms": ms, "polys_per_s": n / (ms * 1e-3),
+            "qr_steps_per_s": 50 * n / (ms * 1e-3),
+            "note": "Alg. 2 mode: 10 QR steps per level, FP32 sweeps + FP64 polish; the paper's "
+                    "own FPGA design reports 16.5e6 QR decompositions/s and its RTX 3060 "
+                    "implementation 2.79e7 polys/s (other hardware, context only)"}
+        log(f"fixed T=10: {ms:.3f} ms, {n / (ms * 1e-3):.3e} polys/s")
     if not args.no_cpu_baseline and args.profile_only is None:
         log("cpu baseline (oracle)")
         cb, oroots, ns = cpu_baseline(a_host)

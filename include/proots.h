@@ -76,8 +76,12 @@ typedef enum pr_precision {
 
 /* Option flags. */
 enum pr_solve_flags {
-    PR_FLAG_NO_EXCEPTIONAL_SHIFT = 1u << 0  /* debug: pure Rayleigh shift only (a polynomial
+    PR_FLAG_NO_EXCEPTIONAL_SHIFT = 1u << 0, /* debug: pure Rayleigh shift only (a polynomial
                                                such as z^d - c then stalls to the cap) */
+    PR_FLAG_FIXED_STEPS = 1u << 1           /* Alg. 2 literally: every level takes exactly
+                                               max_iter_per_level QR steps with the pure
+                                               Rayleigh shift, no convergence test and no
+                                               exceptional shift; NOT_CONVERGED is never set */
 };
 
 /* Options of pr_solve.  Zero-initialised = defaults. */

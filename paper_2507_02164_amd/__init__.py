@@ -10,7 +10,7 @@ The computation lives in hand-written HIP kernels for gfx950 behind a C ABI
 (include/proots.h, libproots.so); this package only marshals torch tensors
 into it.  Build with ``python -m paper_2507_02164_amd.build``.
 """
-from ._capi import (FLAG_NO_EXCEPTIONAL_SHIFT, FP32_POLISH, FP64, PR_ERR_HIP, PR_ERR_INVALID_ARG,
+from ._capi import (FLAG_FIXED_STEPS, FLAG_NO_EXCEPTIONAL_SHIFT, FP32_POLISH, FP64, PR_ERR_HIP, PR_ERR_INVALID_ARG,
                     PR_ERR_UNSUPPORTED, PR_OK, ST_BAD_DEGREE, ST_NONFINITE, ST_NOT_CONVERGED,
                     ST_POLISH_UNCONVERGED, ST_SINGULAR_DERIV, ST_ZERO_LEADING, ProotsError,
                     SolveOpts, backward, density, lib, solve, strerror, version)
@@ -18,7 +18,7 @@ from .autograd import RootsFn, roots
 
 __all__ = [
     "solve", "density", "backward", "RootsFn", "roots", "lib", "strerror", "version",
-    "ProotsError", "SolveOpts", "FP64", "FP32_POLISH", "FLAG_NO_EXCEPTIONAL_SHIFT",
+    "ProotsError", "SolveOpts", "FP64", "FP32_POLISH", "FLAG_NO_EXCEPTIONAL_SHIFT", "FLAG_FIXED_STEPS",
     "PR_OK", "PR_ERR_INVALID_ARG", "PR_ERR_UNSUPPORTED", "PR_ERR_HIP",
     "ST_BAD_DEGREE", "ST_NONFINITE", "ST_ZERO_LEADING", "ST_NOT_CONVERGED",
     "ST_POLISH_UNCONVERGED", "ST_SINGULAR_DERIV",

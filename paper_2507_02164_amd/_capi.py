@@ -31,6 +31,7 @@ FP32_POLISH = 1
 PRECISIONS = {"fp64": FP64, "fp32_polish": FP32_POLISH}
 
 FLAG_NO_EXCEPTIONAL_SHIFT = 1 << 0
+FLAG_FIXED_STEPS = 1 << 1
 
 
 class ProotsError(RuntimeError):

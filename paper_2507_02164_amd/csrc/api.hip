@@ -59,7 +59,7 @@ extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_
         return PR_ERR_INVALID_ARG;
     if (!(o.polish_tol >= 0.0 && o.polish_tol < 1.0))
         return PR_ERR_INVALID_ARG;
-    if (o.flags & ~(uint32_t)PR_FLAG_NO_EXCEPTIONAL_SHIFT)
+    if (o.flags & ~(uint32_t)(PR_FLAG_NO_EXCEPTIONAL_SHIFT | PR_FLAG_FIXED_STEPS))
         return PR_ERR_UNSUPPORTED;
     if (o.tile < -1 || o.tile > max_tile() || o.grid_blocks < 0)
         return PR_ERR_INVALID_ARG;

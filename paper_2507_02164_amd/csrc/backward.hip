@@ -19,6 +19,32 @@ namespace proots {
 namespace {
 
 constexpr int kBlock = 256;
+#ifndef PR_BACKWARD_NT
+#define PR_BACKWARD_NT 0
+#endif
+
+// Streaming accesses: every byte is touched once, so keep it out of the caches.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 ld(const double2* p)
+{
+#if PR_BACKWARD_NT
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+    return make_double2(v.x, v.y);
+#else
+    return *p;
+#endif
+}
+
+__device__ __forceinline__ void st2(double2* p, double2 v)
+{
+#if PR_BACKWARD_NT
+    dvec2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<dvec2*>(p));
+#else
+    *p = v;
+#endif
+}
 
 template <int DM>
 __global__ __launch_bounds__(kBlock) void backward_kernel(
@@ -38,33 +64,41 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
     const bool valid = d >= 1 && d <= DM &&
                        !(st & (PR_ST_BAD_DEGREE | PR_ST_NONFINITE | PR_ST_ZERO_LEADING));
     if (valid) {
-        cx<double> a[DM + 1];
+        // every load first (all rows in flight together), then the arithmetic
+        cx<double> a[DM + 1], r[DM], gr[DM];
 #pragma unroll
         for (int k = 0; k <= DM; ++k) {
             a[k] = {0.0, 0.0};
             if (k <= d) {
-                double2 v = coeffs[(int64_t)k * n + i];
+                double2 v = ld(coeffs + (int64_t)k * n + i);
                 a[k] = {v.x, v.y};
             }
         }
 #pragma unroll
         for (int j = 0; j < DM; ++j) {
+            r[j] = gr[j] = {0.0, 0.0};
             if (j < d) {
-                const double2 rv = roots[(int64_t)j * n + i];
-                const double2 gv = grad_roots[(int64_t)j * n + i];
-                const cx<double> r = {rv.x, rv.y};
+                const double2 rv = ld(roots + (int64_t)j * n + i);
+                const double2 gv = ld(grad_roots + (int64_t)j * n + i);
+                r[j] = {rv.x, rv.y};
+                gr[j] = {gv.x, gv.y};
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < DM; ++j) {
+            if (j < d) {
                 // p'(r) by Horner over k = DM..1 (a_k = 0 above the degree)
                 cx<double> dp = {DM * a[DM].re, DM * a[DM].im};
 #pragma unroll
                 for (int k = DM - 1; k >= 1; --k)
-                    dp = dp * r + cx<double>{k * a[k].re, k * a[k].im};
-                if (!finite(dp) || (dp.re == 0.0 && dp.im == 0.0)) {
+                    dp = dp * r[j] + cx<double>{k * a[k].re, k * a[k].im};
+                const bool singular = !finite(dp) || (dp.re == 0.0 && dp.im == 0.0);
+                if (singular)
                     st |= PR_ST_SINGULAR_DERIV;
-                    continue;
-                }
-                // q = -g / conj(dp)
-                cx<double> q = cdiv(cx<double>{-gv.x, -gv.y}, conj(dp));
-                const cx<double> rc = conj(r);
+                // q = -g / conj(dp); a singular root contributes nothing
+                cx<double> q = cdiv(cx<double>{-gr[j].re, -gr[j].im}, conj(dp));
+                q = singular ? cx<double>{0.0, 0.0} : q;
+                const cx<double> rc = conj(r[j]);
 #pragma unroll
                 for (int k = 0; k <= DM; ++k) {
                     if (k <= d)
@@ -76,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
     }
 #pragma unroll
     for (int k = 0; k <= DM; ++k)
-        grad_coeffs[(int64_t)k * n + i] = make_double2(g[k].re, g[k].im);
+        st2(grad_coeffs + (int64_t)k * n + i, make_double2(g[k].re, g[k].im));
     status[i] = st;
 }
 

@@ -9,15 +9,15 @@
 // pixel decision is reproducible from the root array alone, and integer
 // addition makes the image independent of the order of the additions.
 //
-// One lane per polynomial; the wave walks the root rows together, so each
-// row load is a coalesced 16-byte-per-lane read.  Neighbouring polynomials
-// of a smooth family put their roots into the same few pixels, and 64 lanes
-// hammering one address serialise in the memory system.  So each wave first
-// merges equal pixels: the lowest pending lane's pixel is broadcast, every
-// lane holding that pixel is counted with one ballot, and one lane adds the
-// count.  After kRounds merges the remaining lanes add 1 each directly, so a
-// wave of 64 distinct pixels (random roots) costs little more than plain
-// atomics.
+// One lane per polynomial.  All of a lane's root rows are loaded first
+// (coalesced 16-byte-per-lane reads, all in flight together), then binned.
+// Neighbouring polynomials of a smooth family put their roots into the same
+// few pixels, and 64 lanes hammering one address serialise in the memory
+// system, so for each root row the wave merges equal pixels: the lowest
+// pending lane's pixel is broadcast, every lane holding it is counted with
+// one ballot, and one lane adds the count.  After kRounds merges the
+// remaining lanes add 1 each directly, so a row of 64 distinct pixels
+// (random roots) costs little more than plain atomics.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -27,56 +27,92 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kRounds = 8;
+#ifndef PR_DENSITY_XCD_REMAP
+#define PR_DENSITY_XCD_REMAP 1
+#endif
 
+template <int DM>
 __global__ __launch_bounds__(kBlock) void density_kernel(
     const double2* __restrict__ roots, const int32_t* __restrict__ degrees,
-    const uint32_t* __restrict__ status, uint32_t skip_mask, int64_t n, int dmax, double x0,
-    double y0, double sx, double sy, int width, int height, int32_t* __restrict__ hist)
+    const uint32_t* __restrict__ status, uint32_t skip_mask, int64_t n, double x0, double y0,
+    double sx, double sy, int width, int height, int32_t* __restrict__ hist)
 {
 #pragma clang fp contract(off)
+#if PR_DENSITY_XCD_REMAP
+    // consecutive blocks are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous range of polynomials instead, so that neighbouring
+    // polynomials (which hit the same pixels) run on the same XCD
+    const int64_t nb = gridDim.x, per = (nb + 7) / 8;
+    const int64_t b = blockIdx.x;
+    const int64_t bb = (b % 8) * per + b / 8;
+    const int64_t i = bb * kBlock + threadIdx.x;
+#else
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+#endif
     int d = 0;
     if (i < n && !(status && (status[i] & skip_mask))) {
-        d = degrees ? degrees[i] : dmax;
-        d = d > dmax ? dmax : d;
+        d = degrees ? degrees[i] : DM;
+        d = d > DM ? DM : d;
     }
     const double w = (double)width, hgt = (double)height;
-    const int lane = __lane_id();
-    for (int k = 0; k < dmax; ++k) {          // dmax is uniform: every lane takes every trip
-        int bin = -1;
+    int bin[DM];
+#pragma unroll
+    for (int k = 0; k < DM; ++k) {
+        bin[k] = -1;
         if (k < d) {
             const double2 z = roots[(int64_t)k * n + i];
             const double u = (z.x - x0) * sx;
             const double v = (z.y - y0) * sy;
             if (u >= 0.0 && u < w && v >= 0.0 && v < hgt)
-                bin = (int)v * width + (int)u;
+                bin[k] = (int)v * width + (int)u;
         }
-        uint64_t pending = __ballot(bin >= 0);
+    }
+    const int lane = __lane_id();
+#pragma unroll
+    for (int k = 0; k < DM; ++k) {
+        int b = bin[k];
+        uint64_t pending = __ballot(b >= 0);
         for (int round = 0; round < kRounds && pending; ++round) {
             const int leader = __builtin_ctzll(pending);
-            const int b = __builtin_amdgcn_readlane(bin, leader);
-            const uint64_t same = __ballot(bin == b);
+            const int lb = __builtin_amdgcn_readlane(b, leader);
+            const uint64_t same = __ballot(b == lb);
             if (lane == leader)
-                atomicAdd(hist + b, __builtin_popcountll(same));
-            if (bin == b)
-                bin = -1;
+                atomicAdd(hist + lb, __builtin_popcountll(same));
+            if (b == lb)
+                b = -1;
             pending &= ~same;
         }
-        if (bin >= 0)
-            atomicAdd(hist + bin, 1);
+        if (b >= 0)
+            atomicAdd(hist + b, 1);
     }
+}
+
+template <int DM>
+hipError_t launch_dm(const DensityArgs& a, hipStream_t stream)
+{
+    int64_t blocks = (a.n + kBlock - 1) / kBlock;
+#if PR_DENSITY_XCD_REMAP
+    blocks = (blocks + 7) / 8 * 8;
+#endif
+    hipLaunchKernelGGL(density_kernel<DM>, dim3((unsigned)blocks), dim3(kBlock), 0, stream,
+                       reinterpret_cast<const double2*>(a.roots), a.degrees, a.status,
+                       a.skip_mask, a.n, a.x0, a.y0, a.sx, a.sy, a.width, a.height, a.hist);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_density(const DensityArgs& a, hipStream_t stream)
 {
-    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(density_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const double2*>(a.roots), a.degrees, a.status,
-                       a.skip_mask, a.n, a.dmax, a.x0, a.y0, a.sx, a.sy, a.width, a.height,
-                       a.hist);
-    return hipGetLastError();
+    switch (a.dmax) {
+    case 1: return launch_dm<1>(a, stream);
+    case 2: return launch_dm<2>(a, stream);
+    case 3: return launch_dm<3>(a, stream);
+    case 4: return launch_dm<4>(a, stream);
+    case 5: return launch_dm<5>(a, stream);
+    case 6: return launch_dm<6>(a, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace proots

@@ -47,7 +47,10 @@
 namespace proots {
 namespace {
 
-constexpr int kBlock = 256;
+#ifndef PR_SOLVE_BLOCK
+#define PR_SOLVE_BLOCK 64
+#endif
+constexpr int kBlock = PR_SOLVE_BLOCK;
 
 // ---------------------------------------------------------------- Givens
 // (c, s) = (conj a, conj b) / rho, rho = sqrt(|a|^2 + |b|^2): the only pair
@@ -163,16 +166,17 @@ struct Eps<float> {
 // below level M ride along with the identity.
 template <typename T, int DM, int M, typename Emit>
 __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int cap, bool exc,
-                                     uint32_t& st, int32_t* __restrict__ iters, int64_t n,
-                                     int64_t i, Emit&& emit)
+                                     bool fixed, uint32_t& st, int32_t* __restrict__ iters,
+                                     int64_t n, int64_t i, Emit&& emit)
 {
     const bool here = m == M;
     const double hh = cabs1_d(h[M - 1][M - 2]);
     const double tt = cabs1_d(h[M - 1][M - 1]) + cabs1_d(h[M - 2][M - 2]);
-    const bool conv = hh <= Eps<T>::v * tt;
+    // fixed-step mode (Alg. 2): no test, exactly `cap` steps per level
+    const bool conv = !fixed && hh <= Eps<T>::v * tt;
     const bool done = here && (conv || its == cap);
     if (done) {
-        if (!conv)
+        if (!conv && !fixed)
             st |= PR_ST_NOT_CONVERGED;
         if (iters)
             iters[(int64_t)(M - 2) * n + i] = its;
@@ -196,26 +200,35 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int c
 // Keeping the wave level-synchronous wastes less work on lane divergence
 // than letting every lane run its own level (a trip would then execute the
 // union of the levels present), and a separate loop per level lets each
-// loop carry only its own M x M block in registers.
+// loop carry only its own M x M block in registers.  The loop body holds two
+// trips (with the wave-uniform exit test between them): a one-trip body ends
+// with the rotated entries in other registers than it started with, and the
+// copies back at the loop edge cost both instructions and, above all,
+// registers; over two trips the register assignment closes up.
 template <typename T, int DM, int M, typename Emit>
 __device__ __forceinline__ void iterate_from(cx<T> (&h)[DM][DM], int& m, int& its, int cap,
-                                             bool exc, uint32_t& st, int32_t* __restrict__ iters,
-                                             int64_t n, int64_t i, Emit&& emit)
+                                             bool exc, bool fixed, uint32_t& st,
+                                             int32_t* __restrict__ iters, int64_t n, int64_t i,
+                                             Emit&& emit)
 {
     if constexpr (M >= 2) {
-        while (__ballot(m == M))
-            trip<T, DM, M>(h, m, its, cap, exc, st, iters, n, i, emit);
-        iterate_from<T, DM, M - 1>(h, m, its, cap, exc, st, iters, n, i, emit);
+        while (__ballot(m == M)) {
+            trip<T, DM, M>(h, m, its, cap, exc, fixed, st, iters, n, i, emit);
+            if (!__ballot(m == M))
+                break;
+            trip<T, DM, M>(h, m, its, cap, exc, fixed, st, iters, n, i, emit);
+        }
+        iterate_from<T, DM, M - 1>(h, m, its, cap, exc, fixed, st, iters, n, i, emit);
     }
 }
 
 template <typename T, int DM, typename Emit>
 __device__ __forceinline__ void iterate(cx<T> (&h)[DM][DM], int d, int cap, bool exc,
-                                        uint32_t& st, int32_t* __restrict__ iters, int64_t n,
-                                        int64_t i, Emit&& emit)
+                                        bool fixed, uint32_t& st, int32_t* __restrict__ iters,
+                                        int64_t n, int64_t i, Emit&& emit)
 {
     int m = d, its = 0;
-    iterate_from<T, DM, DM>(h, m, its, cap, exc, st, iters, n, i, emit);
+    iterate_from<T, DM, DM>(h, m, its, cap, exc, fixed, st, iters, n, i, emit);
 }
 
 // Companion matrix, first-row form: h[0][j] = -b_{d-1-j} for j < d, ones on
@@ -352,10 +365,11 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
         for (int c = (r > 0 ? r - 1 : 0); c < DM; ++c)
             h[r][c] = {T(0), T(0)};
     companion<T, DM>(h, dd, b);
-    const bool exc = !(io.flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT);
+    const bool fixed = (io.flags & PR_FLAG_FIXED_STEPS) != 0;
+    const bool exc = !(io.flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT) && !fixed;
 
     if constexpr (!FP32) {
-        iterate<double, DM>(h, dd, io.cap, exc, st, io.iters, n, i, [&](int k, cx<double> v) {
+        iterate<double, DM>(h, dd, io.cap, exc, fixed, st, io.iters, n, i, [&](int k, cx<double> v) {
             io.roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
         });
         if (ok)
@@ -365,7 +379,7 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
 #pragma unroll
         for (int k = 0; k < DM; ++k)
             e[k] = {0.0f, 0.0f};
-        iterate<float, DM>(h, dd, io.cap, exc, st, io.iters, n, i, [&](int k, cx<float> v) {
+        iterate<float, DM>(h, dd, io.cap, exc, fixed, st, io.iters, n, i, [&](int k, cx<float> v) {
             // k is a compile-time constant after inlining
 #pragma unroll
             for (int q = 0; q < DM; ++q)

@@ -269,3 +269,28 @@ def test_tile_argument_validation():
     for bad in (dict(tile=-2), dict(tile=4097), dict(grid_blocks=-1)):
         with pytest.raises(pr.ProotsError):
             pr.solve(a, d, "fp64", **bad)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
+def test_fixed_steps_mode_matches_oracle_and_paper_counts(precision):
+    """Alg. 2 literally: T steps per level, (n-1) T = 50 in all for n = 6,
+    T = 10 (Table III); roots agree with the oracle's fixed-T mode."""
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_fixed_T.json")))
+    T = g["T"]
+    a = workloads.gaussian(8192, seed=12)
+    ref, ref_st, ref_it = oracle.solve(a, fixed_t=T, return_iters=True)
+    got, st, it = _solve(a, None, precision, flags=pr.FLAG_FIXED_STEPS, max_iter_per_level=T,
+                         iter_counts=True)
+    assert np.all(it == T) and np.all(it.sum(axis=0) == g["qr_steps_per_poly"])
+    assert np.all((st & pr.ST_NOT_CONVERGED) == 0)
+    if precision == "fp64":
+        err = rel_err(match(got, ref), ref)
+        assert np.quantile(err, 0.99) < 1e-10
+        assert np.median(err) < 1e-14
+    else:
+        # the polish takes the fixed-T FP32 roots to the converged roots
+        conv, _ = oracle.solve(a)
+        ok = (st & pr.ST_POLISH_UNCONVERGED) == 0
+        err = rel_err(match(got[:, ok], conv[:, ok]), conv[:, ok])
+        assert ok.mean() > 0.95 and np.quantile(err, 0.99) < 1e-10
