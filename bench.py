@@ -137,6 +137,40 @@ def bench_mixed(args, torch, workloads, pr, dev):
     print(json.dumps({"workload": "mixed degrees 2..6, 64Mi polynomials", "n": n, "results": out}))
 
 
+def bench_l2fit(args, torch, pr, dev, n=1 << 21, degree=6, nr=8, nt=16):
+    """Sec. II-A front-end on its own: degree-6 least-squares fits of
+    f(z) = sin z on 2^21 disks from 8 x 16 polar samples each.  HBM-bound:
+    16 bytes read per sample and 16 written per coefficient."""
+    log(f"l2fit: {n} disks, degree {degree}, {nr}x{nt} samples")
+    g = torch.Generator(device="cpu").manual_seed(3)
+    c = torch.complex(torch.rand(n, generator=g, dtype=torch.float64) * 8 - 4,
+                      torch.rand(n, generator=g, dtype=torch.float64) * 3 - 1.5).to(dev)
+    rho = torch.full((n,), 0.0375, dtype=torch.float64, device=dev)
+    nodes, _ = pr.l2fit_nodes(nr, nt)
+    w = torch.from_numpy(nodes).to(dev)
+    samples = torch.sin(c[None, :] + rho[None, :] * w[:, None]).contiguous()
+    coeffs = torch.empty((degree + 1, n), dtype=torch.complex128, device=dev)
+    for _ in range(max(args.warmup, 1)):
+        pr.l2fit(samples, degree, nr, nt, coeffs=coeffs)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(args.steps):
+        pr.l2fit(samples, degree, nr, nt, coeffs=coeffs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nbytes = n * (nr * nt + degree + 1) * 16
+    log(f"l2fit: {ms:.3f} ms, {nbytes / (ms * 1e-3) / 1e9:.0f} GB/s")
+    del samples
+    return {"n_disks": n, "degree": degree, "samples_per_disk": nr * nt, "ms": ms,
+            "disks_per_s": n / (ms * 1e-3), "alg_bytes_per_launch": nbytes,
+            "achieved_GBps": nbytes / (ms * 1e-3) / 1e9,
+            "hbm_frac": nbytes / (ms * 1e-3) / PEAK_HBM}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +336,7 @@ def main():
                     "own FPGA design reports 16.5e6 QR decompositions/s and its RTX 3060 "
                     "implementation 2.79e7 polys/s (other hardware, context only)"}
         log(f"fixed T=10: {ms:.3f} ms, {n / (ms * 1e-3):.3e} polys/s")
+        out["l2fit_front_end"] = bench_l2fit(args, torch, pr, dev)
     if not args.no_cpu_baseline and args.profile_only is None:
         log("cpu baseline (oracle)")
         cb, oroots, ns = cpu_baseline(a_host)

@@ -174,6 +174,55 @@ int pr_backward(const pr_complex* coeffs, const int32_t* degrees, const pr_compl
                 const pr_complex* grad_roots, int64_t n, int32_t dmax, pr_complex* grad_coeffs,
                 uint32_t* status, void* stream);
 
+/*
+ * The polynomial-approximation front-end (Sec. II-A): a complex function f is
+ * approximated on each small disk D_i = {c_i + rho_i w : |w| < 1} by the
+ * polynomial g_i(w) = sum_{k<=degree} a_k w^k of least L2 error, with the
+ * inner product <g, h> = integral over the unit disk of g(w) conj(h(w)) dA.
+ * The normal equations G a = b have G_jk = <w^j, w^k> = pi/(j+1) delta_jk
+ * and b_j = <f, w^j>, so a_j = (j+1)/pi * b_j.  b_j is computed by a product
+ * quadrature in polar coordinates: nr Gauss-Legendre nodes in the radius
+ * (weights carrying the r dr area factor) times nt equally spaced angles.
+ * For f a polynomial of degree D the quadrature, and so the fit, is exact
+ * when D + degree + 1 <= 2 nr - 1 and D + degree < nt.  Node q = ir * nt + it
+ * sits at w_q = r_ir exp(2 pi i it / nt).
+ *
+ * pr_l2fit_nodes -- HOST call: the nr*nt quadrature nodes w_q (interleaved
+ *   re, im: nodes[2q], nodes[2q+1]) and weights (including the r dr factor,
+ *   summing to pi) at which the caller samples f(c_i + rho_i w_q).
+ *   nodes [2*nr*nt] and weights [nr*nt] are HOST arrays owned by the caller.
+ *   Errors: PR_ERR_INVALID_ARG for NULL arrays, nr outside 1..64 or nt
+ *   outside 1..256.
+ */
+int pr_l2fit_nodes(int32_t nr, int32_t nt, double* nodes, double* weights);
+
+/*
+ * pr_l2fit -- coefficients of the degree-`degree` L2 approximation on each
+ * of n disks, in the disk's local variable w.
+ *   samples  [nr*nt][n] pr_complex: row q holds f at node w_q of every disk.
+ *   coeffs   [dmax+1][n] pr_complex out (dmax = degree), ready for pr_solve
+ *            (whose roots are then local w; pr_density_local maps them back).
+ * Errors: PR_ERR_INVALID_ARG for NULL arrays, n < 0, degree outside 1..6,
+ * nr outside 1..64 or nt outside 1..256; PR_ERR_HIP if a launch fails.
+ */
+int pr_l2fit(const pr_complex* samples, int64_t n, int32_t degree, int32_t nr, int32_t nt,
+             pr_complex* coeffs, void* stream);
+
+/*
+ * pr_density_local -- pr_density for roots in local disk coordinates:
+ * a root w of polynomial i counts only if |w|^2 < rmax2 (the zero lies in
+ * the disk the polynomial approximates f on); it is mapped to
+ * z = c_i + rho_i w (re and im each a correctly rounded FP64 multiply then
+ * add) and binned exactly as pr_density bins z.
+ *   centers [n] pr_complex c_i, radii [n] double rho_i (DEVICE arrays).
+ * Other arguments and errors as pr_density; PR_ERR_INVALID_ARG also for
+ * NULL centers/radii or rmax2 not > 0.
+ */
+int pr_density_local(const pr_complex* roots, const int32_t* degrees, const uint32_t* status,
+                     uint32_t skip_mask, int64_t n, int32_t dmax, const pr_complex* centers,
+                     const double* radii, double rmax2, double x0, double x1, double y0,
+                     double y1, int32_t width, int32_t height, int32_t* hist, void* stream);
+
 /* Static English text for a return code. */
 const char* pr_strerror(int code);
 

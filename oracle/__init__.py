@@ -65,6 +65,11 @@ def _load():
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, P]
         lib.oracle_density.restype = None
+        lib.oracle_density_local.argtypes = [P, P, P, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int,
+                                             P, P, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int, ctypes.c_int, P]
+        lib.oracle_density_local.restype = None
         lib.oracle_backward.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int]
         lib.oracle_backward.restype = None
         lib.oracle_givens.argtypes = [P, P, P, P]
@@ -140,6 +145,54 @@ def density(roots, window, shape, degrees=None, status=None, skip_mask: int = 0,
     _load().oracle_density(_ptr(roots), _ptr(deg), _ptr(st), skip_mask, n, dmax,
                            x0, x1, y0, y1, width, height, _ptr(out))
     return out
+
+
+def density_local(roots, centers, radii, window, shape, rmax2=1.0, degrees=None, status=None,
+                  skip_mask: int = 0, out=None):
+    """``density`` for roots in local disk coordinates w: a root counts iff
+    |w|^2 < rmax2, placed at centers[i] + radii[i] * w."""
+    roots = _c128(roots)
+    dmax, n = roots.shape
+    centers = _c128(centers, (n,))
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
+    x0, x1, y0, y1 = (float(v) for v in window)
+    width, height = (int(v) for v in shape)
+    if out is None:
+        out = np.zeros((height, width), dtype=np.int32)
+    deg = _degrees(degrees, n)
+    st = None if status is None else np.ascontiguousarray(status, dtype=np.uint32)
+    _load().oracle_density_local(_ptr(roots), _ptr(deg), _ptr(st), skip_mask, n, dmax,
+                                 _ptr(centers), _ptr(radii), float(rmax2), x0, x1, y0, y1,
+                                 width, height, _ptr(out))
+    return out
+
+
+def l2_nodes(nr: int, nt: int):
+    """Product quadrature on the unit disk (Sec. II-A inner product):
+    nr Gauss-Legendre radii (numpy's rule mapped to [0, 1], weight r dr) times
+    nt equally spaced angles.  Returns (nodes complex [nr*nt], weights)."""
+    x, w = np.polynomial.legendre.leggauss(nr)
+    r = 0.5 * (x + 1.0)
+    wr = 0.5 * w * r
+    th = 2.0 * np.pi * np.arange(nt) / nt
+    nodes = (r[:, None] * np.exp(1j * th)[None, :]).ravel()
+    weights = np.repeat(wr * (2.0 * np.pi / nt), nt)
+    return nodes, weights
+
+
+def l2fit(samples, nodes, weights, degree):
+    """Sec. II-A: coefficients a of the polynomial p(w) = sum_k a_k w^k that
+    minimises ||f - p|| for <g, h> = integral over the unit disk of g conj(h),
+    from the normal equations G a = b with G_jk = <w^j, w^k> and
+    b_j = <f, w^j>, both by the given quadrature (G is assembled in full and
+    solved, not assumed diagonal).  samples [Q, n] -> coefficients
+    [degree+1, n]."""
+    samples = np.asarray(samples, dtype=np.complex128)
+    V = nodes[None, :] ** np.arange(degree + 1)[:, None]             # [deg+1, Q]: w^j
+    G = (V * weights[None, :]) @ V.conj().T                          # <w^j, w^k> = sum w_q^j conj(w_q^k)
+    # G_jk = <z^j, z^k> = integral z^j conj(z)^k: row j, column k
+    B = (V.conj() * weights[None, :]) @ samples                      # b_j = sum f conj(w^j)
+    return np.linalg.solve(G.T, B)                                    # sum_k G_kj a_k = b_j
 
 
 def backward(coeffs, roots, grad_roots, degrees=None, status=None, nthreads: int = 0):

@@ -305,6 +305,37 @@ void oracle_density(const double *roots, const int32_t *degrees, const uint32_t 
     }
 }
 
+/* Roots-to-pixels for roots in local disk coordinates (the approximation
+ * front-end, Sec. II-A): root w of polynomial i counts only if
+ * |w|^2 < rmax2 (the zero lies in the disk where the polynomial approximates
+ * f); it is placed at z = c_i + rho_i w and counted as in oracle_density. */
+void oracle_density_local(const double *roots, const int32_t *degrees, const uint32_t *status,
+                          uint32_t skip_mask, int64_t n, int dmax, const double *centers,
+                          const double *radii, double rmax2, double x0, double x1, double y0,
+                          double y1, int width, int height, int32_t *hist)
+{
+    double sx = (double)width / (x1 - x0);
+    double sy = (double)height / (y1 - y0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (status && (status[i] & skip_mask))
+            continue;
+        int d = degrees ? degrees[i] : dmax;
+        if (d > dmax)
+            d = dmax;
+        for (int k = 0; k < d; ++k) {
+            double wr = roots[2 * (k * n + i)], wi = roots[2 * (k * n + i) + 1];
+            if (!(wr * wr + wi * wi < rmax2))
+                continue;
+            double re = centers[2 * i] + radii[i] * wr;
+            double im = centers[2 * i + 1] + radii[i] * wi;
+            double u = (re - x0) * sx;
+            double v = (im - y0) * sy;
+            if (u >= 0.0 && u < (double)width && v >= 0.0 && v < (double)height)
+                hist[(int64_t)(int)v * width + (int)u] += 1;
+        }
+    }
+}
+
 /* Implicit-function adjoint.  At a simple root r of p(z) = sum_k a_k z^k,
  * p(r(a); a) = 0 gives dr/da_k = -r^k / p'(r).  For a real loss L with
  * cotangent g_r = dL/dRe r + i dL/dIm r, the cotangent of a_k (same

@@ -72,6 +72,12 @@ def lib() -> ctypes.CDLL:
         L.pr_density.restype = ctypes.c_int
         L.pr_backward.argtypes = [P, P, P, P, I64, I32, P, P, P]
         L.pr_backward.restype = ctypes.c_int
+        L.pr_density_local.argtypes = [P, P, P, U32, I64, I32, P, P, D, D, D, D, D, I32, I32, P, P]
+        L.pr_density_local.restype = ctypes.c_int
+        L.pr_l2fit_nodes.argtypes = [I32, I32, P, P]
+        L.pr_l2fit_nodes.restype = ctypes.c_int
+        L.pr_l2fit.argtypes = [P, I64, I32, I32, I32, P, P]
+        L.pr_l2fit.restype = ctypes.c_int
         L.pr_strerror.argtypes = [ctypes.c_int]
         L.pr_strerror.restype = ctypes.c_char_p
         L.pr_version.argtypes = []
@@ -209,3 +215,58 @@ def backward(coeffs, roots, grad_roots, degrees=None, status=None, grad_coeffs=N
     if rc != PR_OK:
         raise ProotsError(rc, "pr_backward")
     return grad_coeffs, status
+
+
+def l2fit_nodes(nr: int, nt: int):
+    """Quadrature nodes w_q (complex, [nr*nt]) and weights ([nr*nt], sum pi)
+    on the unit disk at which to sample f for ``l2fit`` (host arrays)."""
+    import numpy as np
+    nodes = np.empty(2 * nr * nt, dtype=np.float64)
+    weights = np.empty(nr * nt, dtype=np.float64)
+    rc = lib().pr_l2fit_nodes(nr, nt, nodes.ctypes.data, weights.ctypes.data)
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_l2fit_nodes")
+    return nodes.view(np.complex128), weights
+
+
+def l2fit(samples, degree: int, nr: int, nt: int, coeffs=None, stream=None):
+    """Least-squares polynomial approximation (Sec. II-A) on each disk:
+    ``samples`` complex128 [nr*nt, n] (f at the ``l2fit_nodes`` of each
+    disk) -> coefficients complex128 [degree+1, n] in the disk's local
+    variable."""
+    _check(samples, "samples", torch.complex128, (nr * nt, samples.shape[1]))
+    n = samples.shape[1]
+    if coeffs is None:
+        coeffs = torch.empty((degree + 1, n), dtype=torch.complex128, device=samples.device)
+    _check(coeffs, "coeffs", torch.complex128, (degree + 1, n))
+    with torch.cuda.device(samples.device):
+        rc = lib().pr_l2fit(_ptr(samples), n, degree, nr, nt, _ptr(coeffs), _stream(stream))
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_l2fit")
+    return coeffs
+
+
+def density_local(roots, centers, radii, window, shape, rmax2=1.0, degrees=None, status=None,
+                  skip_mask=0, out=None, stream=None):
+    """``density`` for roots in local disk coordinates: root w of polynomial
+    i counts iff |w|^2 < rmax2, at z = centers[i] + radii[i] * w."""
+    _check(roots, "roots", torch.complex128)
+    dmax, n = roots.shape
+    _check(centers, "centers", torch.complex128, (n,))
+    _check(radii, "radii", torch.float64, (n,))
+    x0, x1, y0, y1 = (float(v) for v in window)
+    width, height = (int(v) for v in shape)
+    if out is None:
+        out = torch.zeros((height, width), dtype=torch.int32, device=roots.device)
+    _check(out, "out", torch.int32, (height, width))
+    if degrees is not None:
+        _check(degrees, "degrees", torch.int32, (n,))
+    if status is not None:
+        _check(status, "status", torch.int32, (n,))
+    with torch.cuda.device(roots.device):
+        rc = lib().pr_density_local(_ptr(roots), _ptr(degrees), _ptr(status), skip_mask & 0xFFFFFFFF,
+                                    n, dmax, _ptr(centers), _ptr(radii), float(rmax2), x0, x1, y0,
+                                    y1, width, height, _ptr(out), _stream(stream))
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_density_local")
+    return out

@@ -89,10 +89,11 @@ extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_
     return hip_status(launch_solve_fp32_polish(a, s));
 }
 
-extern "C" int pr_density(const pr_complex* roots, const int32_t* degrees,
+static int density_common(const pr_complex* roots, const int32_t* degrees,
                           const uint32_t* status, uint32_t skip_mask, int64_t n, int32_t dmax,
                           double x0, double x1, double y0, double y1, int32_t width,
-                          int32_t height, int32_t* hist, void* stream)
+                          int32_t height, int32_t* hist, const pr_complex* centers,
+                          const double* radii, double rmax2, void* stream)
 {
     if (n < 0 || dmax < 1 || dmax > 6 || !hist)
         return PR_ERR_INVALID_ARG;
@@ -126,7 +127,70 @@ extern "C" int pr_density(const pr_complex* roots, const int32_t* degrees,
     a.width = width;
     a.height = height;
     a.hist = hist;
+    a.centers = centers;
+    a.radii = radii;
+    a.rmax2 = rmax2;
     return hip_status(launch_density(a, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" int pr_density(const pr_complex* roots, const int32_t* degrees,
+                          const uint32_t* status, uint32_t skip_mask, int64_t n, int32_t dmax,
+                          double x0, double x1, double y0, double y1, int32_t width,
+                          int32_t height, int32_t* hist, void* stream)
+{
+    return density_common(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
+                          height, hist, nullptr, nullptr, 0.0, stream);
+}
+
+extern "C" int pr_density_local(const pr_complex* roots, const int32_t* degrees,
+                                const uint32_t* status, uint32_t skip_mask, int64_t n,
+                                int32_t dmax, const pr_complex* centers, const double* radii,
+                                double rmax2, double x0, double x1, double y0, double y1,
+                                int32_t width, int32_t height, int32_t* hist, void* stream)
+{
+    if (!(rmax2 > 0.0) || !std::isfinite(rmax2))
+        return PR_ERR_INVALID_ARG;
+    if (n > 0 && (!centers || !radii))
+        return PR_ERR_INVALID_ARG;
+    return density_common(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
+                          height, hist, centers, radii, rmax2, stream);
+}
+
+extern "C" int pr_l2fit_nodes(int32_t nr, int32_t nt, double* nodes, double* weights)
+{
+    if (!nodes || !weights || nr < 1 || nr > kMaxNr || nt < 1 || nt > kMaxNt)
+        return PR_ERR_INVALID_ARG;
+    L2Quad q;
+    l2_quadrature(nr, nt, q);
+    for (int ir = 0; ir < nr; ++ir)
+        for (int it = 0; it < nt; ++it) {
+            const int k = ir * nt + it;
+            const double th = 2.0 * M_PI * it / nt;
+            nodes[2 * k] = q.r[ir] * std::cos(th);
+            nodes[2 * k + 1] = q.r[ir] * std::sin(th);
+            weights[k] = q.w[ir];
+        }
+    return PR_OK;
+}
+
+extern "C" int pr_l2fit(const pr_complex* samples, int64_t n, int32_t degree, int32_t nr,
+                        int32_t nt, pr_complex* coeffs, void* stream)
+{
+    if (n < 0 || degree < 1 || degree > 6 || nr < 1 || nr > kMaxNr || nt < 1 || nt > kMaxNt)
+        return PR_ERR_INVALID_ARG;
+    if (n > 0 && (!samples || !coeffs))
+        return PR_ERR_INVALID_ARG;
+    if (n == 0)
+        return PR_OK;
+    if (n > (int64_t)0x7fffffff * 256)
+        return PR_ERR_INVALID_ARG;
+    L2FitArgs a;
+    a.samples = samples;
+    a.n = n;
+    a.degree = degree;
+    l2_quadrature(nr, nt, a.quad);
+    a.coeffs = coeffs;
+    return hip_status(launch_l2fit(a, static_cast<hipStream_t>(stream)));
 }
 
 extern "C" int pr_backward(const pr_complex* coeffs, const int32_t* degrees,

@@ -18,6 +18,10 @@
 // one ballot, and one lane adds the count.  After kRounds merges the
 // remaining lanes add 1 each directly, so a row of 64 distinct pixels
 // (random roots) costs little more than plain atomics.
+//
+// Local form (the front-end's roots, in each disk's variable w): a root
+// counts only when |w|^2 < rmax2, at z = c + rho w (each part a rounded
+// multiply then a rounded add), then binned as above.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -31,11 +35,12 @@ constexpr int kRounds = 8;
 #define PR_DENSITY_XCD_REMAP 1
 #endif
 
-template <int DM>
+template <int DM, bool LOCAL>
 __global__ __launch_bounds__(kBlock) void density_kernel(
     const double2* __restrict__ roots, const int32_t* __restrict__ degrees,
     const uint32_t* __restrict__ status, uint32_t skip_mask, int64_t n, double x0, double y0,
-    double sx, double sy, int width, int height, int32_t* __restrict__ hist)
+    double sx, double sy, int width, int height, int32_t* __restrict__ hist,
+    const double2* __restrict__ centers, const double* __restrict__ radii, double rmax2)
 {
 #pragma clang fp contract(off)
 #if PR_DENSITY_XCD_REMAP
@@ -55,12 +60,25 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
         d = d > DM ? DM : d;
     }
     const double w = (double)width, hgt = (double)height;
+    double2 c = make_double2(0.0, 0.0);
+    double rho = 0.0;
+    if (LOCAL && d > 0) {
+        c = centers[i];
+        rho = radii[i];
+    }
     int bin[DM];
 #pragma unroll
     for (int k = 0; k < DM; ++k) {
         bin[k] = -1;
         if (k < d) {
-            const double2 z = roots[(int64_t)k * n + i];
+            double2 z = roots[(int64_t)k * n + i];
+            if (LOCAL) {
+                // local root w: keep it only inside the disk, then z = c + rho w
+                const bool inside = z.x * z.x + z.y * z.y < rmax2;
+                z = make_double2(c.x + rho * z.x, c.y + rho * z.y);
+                if (!inside)
+                    z = make_double2(__builtin_nan(""), 0.0);
+            }
             const double u = (z.x - x0) * sx;
             const double v = (z.y - y0) * sy;
             if (u >= 0.0 && u < w && v >= 0.0 && v < hgt)
@@ -94,9 +112,17 @@ hipError_t launch_dm(const DensityArgs& a, hipStream_t stream)
 #if PR_DENSITY_XCD_REMAP
     blocks = (blocks + 7) / 8 * 8;
 #endif
-    hipLaunchKernelGGL(density_kernel<DM>, dim3((unsigned)blocks), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const double2*>(a.roots), a.degrees, a.status,
-                       a.skip_mask, a.n, a.x0, a.y0, a.sx, a.sy, a.width, a.height, a.hist);
+    if (a.centers)
+        hipLaunchKernelGGL((density_kernel<DM, true>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                           stream, reinterpret_cast<const double2*>(a.roots), a.degrees,
+                           a.status, a.skip_mask, a.n, a.x0, a.y0, a.sx, a.sy, a.width,
+                           a.height, a.hist, reinterpret_cast<const double2*>(a.centers),
+                           a.radii, a.rmax2);
+    else
+        hipLaunchKernelGGL((density_kernel<DM, false>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                           stream, reinterpret_cast<const double2*>(a.roots), a.degrees,
+                           a.status, a.skip_mask, a.n, a.x0, a.y0, a.sx, a.sy, a.width,
+                           a.height, a.hist, nullptr, nullptr, 0.0);
     return hipGetLastError();
 }
 

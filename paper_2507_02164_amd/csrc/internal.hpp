@@ -39,6 +39,11 @@ struct DensityArgs {
     double x0, y0, sx, sy;
     int32_t width, height;
     int32_t* hist;
+    // local-coordinate form: root w of polynomial i counts iff |w|^2 < rmax2
+    // and is binned at centers[i] + radii[i] * w (centers == nullptr: plain)
+    const pr_complex* centers;
+    const double* radii;
+    double rmax2;
 };
 
 hipError_t launch_density(const DensityArgs& a, hipStream_t stream);
@@ -55,5 +60,28 @@ struct BackwardArgs {
 };
 
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t stream);
+
+constexpr int kMaxNr = 64;
+constexpr int kMaxNt = 256;
+
+// Product quadrature on the unit disk: radii r[k] with weights w[k] that
+// already carry the r dr area factor and the 2 pi / nt angular step.
+struct L2Quad {
+    int32_t nr, nt;
+    double r[kMaxNr];
+    double w[kMaxNr];
+};
+
+struct L2FitArgs {
+    const pr_complex* samples;
+    int64_t n;
+    int32_t degree;
+    L2Quad quad;
+    pr_complex* coeffs;
+};
+
+void gauss_legendre(int n, double* x, double* w);
+void l2_quadrature(int nr, int nt, L2Quad& q);
+hipError_t launch_l2fit(const L2FitArgs& a, hipStream_t stream);
 
 }  // namespace proots
