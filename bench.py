@@ -5,8 +5,10 @@ FP32 sweeps + FP64 Newton polish beside plain FP64.
 Workload (default): the 4096 x 4096 parametric grid of monic degree-6
 polynomials a_k = c_k + t1 d_k + t2 e_k (16,777,216 polynomials), binned
 into a 1920 x 1080 root-density image.  One step = the whole path over the
-batch: pr_solve -> pr_density (into a zeroed image) -> pr_backward (seeded
-root cotangents).  Inputs are resident in HBM before timing starts.
+batch: clear the image, pr_solve_bin (solve, and count every root into the
+image in the same launch), pr_backward (seeded root cotangents).  Inputs are
+resident in HBM before timing starts.  The same path as three launches
+(pr_solve, pr_density, pr_backward) is timed beside it.
 
 Prints one JSON line.  `value` is whole-step throughput of the FP32 + polish
 form; the FP64 form is measured the same way and reported beside it.
@@ -36,11 +38,11 @@ PEAK_FP32_NONPACKED = 78.6e12
 PEAK_HBM = 8.0e12            # B/s
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "solve_fp32_polish_parametric4096_traffic.json")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "solve_bin_fp32_polish_parametric4096_traffic.json")
 
 
 def measured_traffic(form, grid):
-    """HBM bytes per launch of the solve kernel from the committed rocprofv3
+    """HBM bytes per launch of the solve + bin kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE record (calibrated against a copy kernel), or
     None when that record does not describe the kernel as it is now (its
     sources changed since the counters were taken) or this workload."""
@@ -236,10 +238,50 @@ def main():
             flops += n * polish_flops(6, 2)
         del its
         stream = torch.cuda.current_stream()
+
+        # the timed step: solve and density in one launch (pr_solve_bin), then
+        # the backward pass
+        evf = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+               for _ in range(args.steps)]
+
+        def step(e=None):
+            hist.zero_()
+            if e: e[0].record(stream)
+            pr.solve_bin(a, win, shape, None, form, roots=roots, status=status, out=hist)
+            if e: e[1].record(stream)
+            pr.backward(a, roots, cot, None, status, grad_coeffs=gcoef)
+            if e: e[2].record(stream)
+
+        log(f"{form}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        log(f"{form}: timing {args.steps} steps")
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(evf[k])
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        fused_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evf]))
+        back_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evf]))
+        res[form] = dict(step_ms=step_ms, solve_bin_ms=fused_ms, backward_ms=back_ms,
+                         polys_per_s=n / (step_ms * 1e-3),
+                         alg_flops_per_poly=flops / n,
+                         mean_qr_steps=float(its_h.sum(axis=0).mean()),
+                         flagged_frac=float((st_h != 0).mean()),
+                         alg_tflops=flops / (fused_ms * 1e-3) / 1e12,
+                         lockstep_efficiency=algorithmic_flops(its_h) / lockstep_flops(its_h),
+                         executed_sweep_tflops=lockstep_flops(its_h) / (fused_ms * 1e-3) / 1e12)
+        log(f"{form}: step {step_ms:.3f} ms, solve+bin {fused_ms:.3f} ms, "
+            f"backward {back_ms:.3f} ms")
+        if args.profile_only is not None:
+            continue
+
+        # the same path as three launches (pr_solve, pr_density, pr_backward)
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)]
               for _ in range(args.steps)]
 
-        def step(e=None):
+        def step_separate(e=None):
             if e: e[0].record(stream)
             pr.solve(a, None, form, roots=roots, status=status)
             if e: e[1].record(stream)
@@ -249,31 +291,23 @@ def main():
             pr.backward(a, roots, cot, None, status, grad_coeffs=gcoef)
             if e: e[3].record(stream)
 
-        log(f"{form}: warmup {args.warmup}")
         for _ in range(args.warmup):
-            step()
+            step_separate()
         torch.cuda.synchronize()
-        log(f"{form}: timing {args.steps} steps")
         t0 = time.perf_counter()
         for k in range(args.steps):
-            step(ev[k])
+            step_separate(ev[k])
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        sep_ms = (time.perf_counter() - t0) * 1e3 / args.steps
         solve_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
         dens_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-        back_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
-        step_ms = wall * 1e3 / args.steps
-        res[form] = dict(step_ms=step_ms, solve_ms=solve_ms, density_ms=dens_ms,
-                         backward_ms=back_ms, polys_per_s=n / (step_ms * 1e-3),
-                         solve_polys_per_s=n / (solve_ms * 1e-3),
-                         alg_flops_per_poly=flops / n,
-                         mean_qr_steps=float(its_h.sum(axis=0).mean()),
-                         flagged_frac=float((st_h != 0).mean()),
-                         alg_tflops=flops / (solve_ms * 1e-3) / 1e12,
-                         lockstep_efficiency=algorithmic_flops(its_h) / lockstep_flops(its_h),
-                         executed_sweep_tflops=lockstep_flops(its_h) / (solve_ms * 1e-3) / 1e12)
-        log(f"{form}: step {step_ms:.3f} ms, solve {solve_ms:.3f} ms, density {dens_ms:.3f} ms, "
-            f"backward {back_ms:.3f} ms")
+        res[form]["separate_launches"] = dict(
+            step_ms=sep_ms, solve_ms=solve_ms, density_ms=dens_ms,
+            backward_ms=float(np.mean([e[2].elapsed_time(e[3]) for e in ev])),
+            polys_per_s=n / (sep_ms * 1e-3), solve_polys_per_s=n / (solve_ms * 1e-3),
+            solve_alg_tflops=flops / (solve_ms * 1e-3) / 1e12)
+        log(f"{form}: separate launches: step {sep_ms:.3f} ms, solve {solve_ms:.3f} ms, "
+            f"density {dens_ms:.3f} ms")
 
     main_form = forms[0]
     r = res[main_form]
@@ -294,20 +328,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"parametric grid {g}x{g}: {n} monic degree-6 complex polynomials "
                                "a_k = c_k + t1 d_k + t2 e_k, 1920x1080 int32 density image, "
-                               "step = solve + density + backward",
+                               "step = solve with density binning in one launch + backward",
                    "n_polys": n, "degree": 6, "image": [1920, 1080], "form": main_form},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(main_form, g),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                     "alg_bytes_per_launch": 212 * n,
-                     "kernel": f"solve_{main_form}",
+                     "alg_bytes_per_launch": 212 * n + 4 * shape[0] * shape[1],
+                     "kernel": f"solve_{main_form} with binning epilogue (pr_solve_bin)",
                      "flops_per_launch": r["alg_flops_per_poly"] * n,
-                     "avg_launch_ms": r["solve_ms"]},
+                     "avg_launch_ms": r["solve_bin_ms"]},
         "forms": res,
     }
     if "fp64" in res and "fp32_polish" in res:
-        out["solve_ratio_fp32polish_over_fp64"] = res["fp64"]["solve_ms"] / res["fp32_polish"]["solve_ms"]
+        out["solve_ratio_fp32polish_over_fp64"] = (res["fp64"]["solve_bin_ms"] /
+                                                   res["fp32_polish"]["solve_bin_ms"])
         out["step_ratio_fp32polish_over_fp64"] = res["fp64"]["step_ms"] / res["fp32_polish"]["step_ms"]
     if main_form == "fp32_polish":
         out["roofline"]["peak_nonpacked"] = PEAK_FP32_NONPACKED / 1e12

@@ -151,6 +151,31 @@ int pr_density(const pr_complex* roots, const int32_t* degrees, const uint32_t* 
                double y1, int32_t width, int32_t height, int32_t* hist, void* stream);
 
 /*
+ * pr_solve_bin -- solve and count in one launch (Sec. III: each eigenvalue
+ * goes straight from the solver to its pixel count, the roots need not be
+ * kept).
+ *
+ * The result is that of pr_solve(coeffs, degrees, n, dmax, roots, status,
+ * opts) followed by pr_density(roots, degrees, status, skip_mask, n, dmax,
+ * x0, x1, y0, y1, width, height, hist) on the same stream: the same roots
+ * and status, and the same counts added to hist, bit for bit (integer
+ * addition does not depend on order).
+ *
+ *   coeffs, degrees, n, dmax, status, opts   as for pr_solve.
+ *   roots      [dmax][n] pr_complex out as for pr_solve, or NULL: the roots
+ *              are counted but not stored.
+ *   skip_mask  polynomials whose final status has a bit of skip_mask set are
+ *              not counted.
+ *   x0..y1, width, height, hist   as for pr_density (hist is accumulated).
+ * Errors: those of pr_solve (except that roots may be NULL) and of
+ * pr_density; PR_ERR_HIP if a launch fails.
+ */
+int pr_solve_bin(const pr_complex* coeffs, const int32_t* degrees, int64_t n, int32_t dmax,
+                 pr_complex* roots, uint32_t* status, const pr_solve_opts* opts,
+                 uint32_t skip_mask, double x0, double x1, double y0, double y1, int32_t width,
+                 int32_t height, int32_t* hist, void* stream);
+
+/*
  * pr_backward -- coefficient cotangents from root cotangents.
  *
  * At a simple root r of p, p(r(a); a) = 0 gives dr/da_k = -r^k / p'(r).

@@ -14,11 +14,11 @@ from ._capi import (FLAG_FIXED_STEPS, FLAG_NO_EXCEPTIONAL_SHIFT, FP32_POLISH, FP
                     PR_ERR_UNSUPPORTED, PR_OK, ST_BAD_DEGREE, ST_NONFINITE, ST_NOT_CONVERGED,
                     ST_POLISH_UNCONVERGED, ST_SINGULAR_DERIV, ST_ZERO_LEADING, ProotsError,
                     SolveOpts, backward, density, density_local, l2fit, l2fit_nodes, lib,
-                    solve, strerror, version)
+                    solve, solve_bin, strerror, version)
 from .autograd import RootsFn, roots
 
 __all__ = [
-    "solve", "density", "backward", "l2fit", "l2fit_nodes", "density_local", "RootsFn", "roots", "lib", "strerror", "version",
+    "solve", "solve_bin", "density", "backward", "l2fit", "l2fit_nodes", "density_local", "RootsFn", "roots", "lib", "strerror", "version",
     "ProotsError", "SolveOpts", "FP64", "FP32_POLISH", "FLAG_NO_EXCEPTIONAL_SHIFT", "FLAG_FIXED_STEPS",
     "PR_OK", "PR_ERR_INVALID_ARG", "PR_ERR_UNSUPPORTED", "PR_ERR_HIP",
     "ST_BAD_DEGREE", "ST_NONFINITE", "ST_ZERO_LEADING", "ST_NOT_CONVERGED",

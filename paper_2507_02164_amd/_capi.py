@@ -70,6 +70,9 @@ def lib() -> ctypes.CDLL:
         L.pr_solve.restype = ctypes.c_int
         L.pr_density.argtypes = [P, P, P, U32, I64, I32, D, D, D, D, I32, I32, P, P]
         L.pr_density.restype = ctypes.c_int
+        L.pr_solve_bin.argtypes = [P, P, I64, I32, P, P, ctypes.POINTER(SolveOpts), U32, D, D, D,
+                                   D, I32, I32, P, P]
+        L.pr_solve_bin.restype = ctypes.c_int
         L.pr_backward.argtypes = [P, P, P, P, I64, I32, P, P, P]
         L.pr_backward.restype = ctypes.c_int
         L.pr_density_local.argtypes = [P, P, P, U32, I64, I32, P, P, D, D, D, D, D, I32, I32, P, P]
@@ -117,15 +120,10 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=None, polish_steps=0,
-          polish_tol=0.0, flags=0, iter_counts=False, roots=None, status=None, stream=None,
-          tile=None, grid_blocks=None):
-    """Roots of each column of ``coeffs`` (complex128 [dmax+1, n], row k =
-    a_k).  Returns ``(roots complex128 [dmax, n], status int32 [n])``, plus
-    the per-level QR step counts int32 [dmax-1, n] when ``iter_counts``.
-    Status bits are the ST_* constants (the int32 holds the uint32 bits).
-    Launch layout and iteration cap left as None come from the autotuner's
-    cache for this GPU (library defaults when nothing was tuned)."""
+def _prepare_solve(coeffs, degrees, precision, max_iter_per_level, polish_steps, polish_tol,
+                   flags, iter_counts, roots, status, tile, grid_blocks, want_roots=True):
+    """Shared argument checks, output allocation and options of pr_solve and
+    pr_solve_bin."""
     _check(coeffs, "coeffs", torch.complex128)
     if coeffs.dim() != 2:
         raise ValueError("coeffs must be 2-D [dmax+1, n]")
@@ -134,9 +132,10 @@ def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=None, po
     dev = coeffs.device
     if degrees is not None:
         _check(degrees, "degrees", torch.int32, (n,))
-    if roots is None:
+    if roots is None and want_roots:
         roots = torch.empty((max(dmax, 0), n), dtype=torch.complex128, device=dev)
-    _check(roots, "roots", torch.complex128, (dmax, n))
+    if roots is not None:
+        _check(roots, "roots", torch.complex128, (dmax, n))
     if status is None:
         status = torch.empty((n,), dtype=torch.int32, device=dev)
     _check(status, "status", torch.int32, (n,))
@@ -156,7 +155,22 @@ def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=None, po
             grid_blocks = tuned.get("grid_blocks", 0)
     opts = SolveOpts(prec, max_iter_per_level, polish_steps, flags, polish_tol,
                      None if its is None or its.numel() == 0 else its.data_ptr(), tile, grid_blocks)
-    with torch.cuda.device(dev):
+    return dmax, n, roots, status, its, opts
+
+
+def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=None, polish_steps=0,
+          polish_tol=0.0, flags=0, iter_counts=False, roots=None, status=None, stream=None,
+          tile=None, grid_blocks=None):
+    """Roots of each column of ``coeffs`` (complex128 [dmax+1, n], row k =
+    a_k).  Returns ``(roots complex128 [dmax, n], status int32 [n])``, plus
+    the per-level QR step counts int32 [dmax-1, n] when ``iter_counts``.
+    Status bits are the ST_* constants (the int32 holds the uint32 bits).
+    Launch layout and iteration cap left as None come from the autotuner's
+    cache for this GPU (library defaults when nothing was tuned)."""
+    dmax, n, roots, status, its, opts = _prepare_solve(
+        coeffs, degrees, precision, max_iter_per_level, polish_steps, polish_tol, flags,
+        iter_counts, roots, status, tile, grid_blocks)
+    with torch.cuda.device(coeffs.device):
         rc = lib().pr_solve(_ptr(coeffs), _ptr(degrees), n, dmax, _ptr(roots), _ptr(status),
                             ctypes.byref(opts), _stream(stream))
     if rc != PR_OK:
@@ -164,6 +178,34 @@ def solve(coeffs, degrees=None, precision="fp64", *, max_iter_per_level=None, po
     if iter_counts:
         return roots, status, its
     return roots, status
+
+
+def solve_bin(coeffs, window, shape, degrees=None, precision="fp64", *, skip_mask=0, out=None,
+              store_roots=True, max_iter_per_level=None, polish_steps=0, polish_tol=0.0, flags=0,
+              iter_counts=False, roots=None, status=None, stream=None, tile=None,
+              grid_blocks=None):
+    """``solve`` and ``density`` in one launch: the roots are counted into
+    the int32 [height, width] image ``out`` (a new zeroed one when None) as
+    they are found.  Returns ``(roots or None, status, image)`` (plus the
+    step counts with ``iter_counts``); with ``store_roots=False`` and no
+    ``roots`` array the roots are not written at all."""
+    dmax, n, roots, status, its, opts = _prepare_solve(
+        coeffs, degrees, precision, max_iter_per_level, polish_steps, polish_tol, flags,
+        iter_counts, roots, status, tile, grid_blocks, want_roots=store_roots)
+    x0, x1, y0, y1 = (float(v) for v in window)
+    width, height = (int(v) for v in shape)
+    if out is None:
+        out = torch.zeros((height, width), dtype=torch.int32, device=coeffs.device)
+    _check(out, "out", torch.int32, (height, width))
+    with torch.cuda.device(coeffs.device):
+        rc = lib().pr_solve_bin(_ptr(coeffs), _ptr(degrees), n, dmax, _ptr(roots), _ptr(status),
+                                ctypes.byref(opts), skip_mask & 0xFFFFFFFF, x0, x1, y0, y1, width,
+                                height, _ptr(out), _stream(stream))
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_solve_bin")
+    if iter_counts:
+        return roots, status, out, its
+    return roots, status, out
 
 
 def density(roots, window, shape, degrees=None, status=None, skip_mask=0, out=None, stream=None):

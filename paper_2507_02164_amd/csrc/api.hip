@@ -40,13 +40,41 @@ int cu_count()
 
 }  // namespace
 
-extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_t n,
+// Window validation shared by the density and binning entry points.
+static int make_window(double x0, double x1, double y0, double y1, int32_t width,
+                       int32_t height, int32_t* hist, BinWindow& w)
+{
+    if (!hist)
+        return PR_ERR_INVALID_ARG;
+    if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(y0) || !std::isfinite(y1))
+        return PR_ERR_INVALID_ARG;
+    if (!(x1 > x0) || !(y1 > y0) || width <= 0 || height <= 0)
+        return PR_ERR_INVALID_ARG;
+    if ((int64_t)width * (int64_t)height > 0x7fffffffLL)
+        return PR_ERR_INVALID_ARG;
+    const double sx = (double)width / (x1 - x0);
+    const double sy = (double)height / (y1 - y0);
+    if (!std::isfinite(sx) || !std::isfinite(sy))
+        return PR_ERR_INVALID_ARG;
+    w.x0 = x0;
+    w.y0 = y0;
+    w.sx = sx;
+    w.sy = sy;
+    w.width = width;
+    w.height = height;
+    w.hist = hist;
+    return PR_OK;
+}
+
+// win == nullptr: plain solve; else the binning epilogue (roots optional).
+static int solve_common(const pr_complex* coeffs, const int32_t* degrees, int64_t n,
                         int32_t dmax, pr_complex* roots, uint32_t* status,
-                        const pr_solve_opts* opts, void* stream)
+                        const pr_solve_opts* opts, const BinWindow* win, uint32_t skip_mask,
+                        void* stream)
 {
     if (n < 0 || dmax < 1 || dmax > 6)
         return PR_ERR_INVALID_ARG;
-    if (n > 0 && (!coeffs || !roots || !status))
+    if (n > 0 && (!coeffs || (!roots && !win) || !status))
         return PR_ERR_INVALID_ARG;
     pr_solve_opts o{};
     if (opts)
@@ -83,10 +111,32 @@ extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_
     a.grid_blocks = 0;
     if (degrees && a.tile > 0)
         a.grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : kDefaultBlocksPerCU * cu_count();
+    a.win = win ? *win : BinWindow{0.0, 0.0, 0.0, 0.0, 0, 0, nullptr};
+    a.skip_mask = skip_mask;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (o.precision == PR_FP64)
         return hip_status(launch_solve_fp64(a, s));
     return hip_status(launch_solve_fp32_polish(a, s));
+}
+
+extern "C" int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_t n,
+                        int32_t dmax, pr_complex* roots, uint32_t* status,
+                        const pr_solve_opts* opts, void* stream)
+{
+    return solve_common(coeffs, degrees, n, dmax, roots, status, opts, nullptr, 0, stream);
+}
+
+extern "C" int pr_solve_bin(const pr_complex* coeffs, const int32_t* degrees, int64_t n,
+                            int32_t dmax, pr_complex* roots, uint32_t* status,
+                            const pr_solve_opts* opts, uint32_t skip_mask, double x0, double x1,
+                            double y0, double y1, int32_t width, int32_t height, int32_t* hist,
+                            void* stream)
+{
+    BinWindow w;
+    const int rc = make_window(x0, x1, y0, y1, width, height, hist, w);
+    if (rc != PR_OK)
+        return rc;
+    return solve_common(coeffs, degrees, n, dmax, roots, status, opts, &w, skip_mask, stream);
 }
 
 static int density_common(const pr_complex* roots, const int32_t* degrees,
@@ -95,20 +145,14 @@ static int density_common(const pr_complex* roots, const int32_t* degrees,
                           int32_t height, int32_t* hist, const pr_complex* centers,
                           const double* radii, double rmax2, void* stream)
 {
-    if (n < 0 || dmax < 1 || dmax > 6 || !hist)
+    if (n < 0 || dmax < 1 || dmax > 6)
         return PR_ERR_INVALID_ARG;
     if (n > 0 && !roots)
         return PR_ERR_INVALID_ARG;
-    if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(y0) || !std::isfinite(y1))
-        return PR_ERR_INVALID_ARG;
-    if (!(x1 > x0) || !(y1 > y0) || width <= 0 || height <= 0)
-        return PR_ERR_INVALID_ARG;
-    if ((int64_t)width * (int64_t)height > 0x7fffffffLL)
-        return PR_ERR_INVALID_ARG;
-    const double sx = (double)width / (x1 - x0);
-    const double sy = (double)height / (y1 - y0);
-    if (!std::isfinite(sx) || !std::isfinite(sy))
-        return PR_ERR_INVALID_ARG;
+    BinWindow w;
+    const int rc = make_window(x0, x1, y0, y1, width, height, hist, w);
+    if (rc != PR_OK)
+        return rc;
     if (n == 0)
         return PR_OK;
     if (n > (int64_t)0x7fffffff * 256)
@@ -120,13 +164,7 @@ static int density_common(const pr_complex* roots, const int32_t* degrees,
     a.skip_mask = skip_mask;
     a.n = n;
     a.dmax = dmax;
-    a.x0 = x0;
-    a.y0 = y0;
-    a.sx = sx;
-    a.sy = sy;
-    a.width = width;
-    a.height = height;
-    a.hist = hist;
+    a.win = w;
     a.centers = centers;
     a.radii = radii;
     a.rmax2 = rmax2;

@@ -1,0 +1,62 @@
+// bin.hpp -- root to pixel, and wave-merged pixel counting (arXiv
+// 2507.02164, Sec. III: each eigenvalue becomes a pixel coordinate whose
+// count is incremented in video memory).  Shared by the density kernel and
+// the solve kernel's binning epilogue, so that both decide every pixel with
+// the same arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace proots {
+
+// The image and its window: pixel (v, u) covers [x0 + u/sx, x0 + (u+1)/sx)
+// x [y0 + v/sy, ...); sx = width / (x1 - x0), sy = height / (y1 - y0) are
+// computed once on the host in FP64.
+struct BinWindow {
+    double x0, y0, sx, sy;
+    int32_t width, height;
+    int32_t* hist;  // [height][width], counts are added
+};
+
+// Pixel index of z, or -1 when z is outside the window (or NaN, which fails
+// every comparison).  u = (re - x0) * sx and v = (im - y0) * sy, each a
+// rounded subtract then a rounded multiply (no contraction), so the decision
+// depends on the root alone.
+__device__ __forceinline__ int pixel_of(double re, double im, const BinWindow& w)
+{
+#pragma clang fp contract(off)
+    const double u = (re - w.x0) * w.sx;
+    const double v = (im - w.y0) * w.sy;
+    if (u >= 0.0 && u < (double)w.width && v >= 0.0 && v < (double)w.height)
+        return (int)v * w.width + (int)u;
+    return -1;
+}
+
+// Add 1 at pixel b (b < 0: nothing) for every lane of the wave; all lanes
+// must call it together.  Neighbouring polynomials of a smooth family put
+// their roots into the same few pixels, and many lanes adding to one
+// address serialise in the memory system, so equal pixels are merged first:
+// the lowest pending lane's pixel is broadcast, every lane holding it is
+// counted with one ballot, and one lane adds the count.  After `rounds`
+// merges the remaining lanes add 1 each, so a wave of distinct pixels costs
+// little more than plain atomics.
+__device__ __forceinline__ void wave_count(int b, int32_t* __restrict__ hist, int rounds = 8)
+{
+    const int lane = __lane_id();
+    uint64_t pending = __ballot(b >= 0);
+    for (int round = 0; round < rounds && pending; ++round) {
+        const int leader = __builtin_ctzll(pending);
+        const int lb = __builtin_amdgcn_readlane(b, leader);
+        const uint64_t same = __ballot(b == lb);
+        if (lane == leader)
+            atomicAdd(hist + lb, __builtin_popcountll(same));
+        if (b == lb)
+            b = -1;
+        pending &= ~same;
+    }
+    if (b >= 0)
+        atomicAdd(hist + b, 1);
+}
+
+}  // namespace proots

@@ -10,27 +10,22 @@
 // addition makes the image independent of the order of the additions.
 //
 // One lane per polynomial.  All of a lane's root rows are loaded first
-// (coalesced 16-byte-per-lane reads, all in flight together), then binned.
-// Neighbouring polynomials of a smooth family put their roots into the same
-// few pixels, and 64 lanes hammering one address serialise in the memory
-// system, so for each root row the wave merges equal pixels: the lowest
-// pending lane's pixel is broadcast, every lane holding it is counted with
-// one ballot, and one lane adds the count.  After kRounds merges the
-// remaining lanes add 1 each directly, so a row of 64 distinct pixels
-// (random roots) costs little more than plain atomics.
+// (coalesced 16-byte-per-lane reads, all in flight together), then binned
+// row by row with the wave merging equal pixels before its atomics
+// (`wave_count`).
 //
 // Local form (the front-end's roots, in each disk's variable w): a root
 // counts only when |w|^2 < rmax2, at z = c + rho w (each part a rounded
 // multiply then a rounded add), then binned as above.
 #include <hip/hip_runtime.h>
 
+#include "bin.hpp"
 #include "internal.hpp"
 
 namespace proots {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRounds = 8;
 #ifndef PR_DENSITY_XCD_REMAP
 #define PR_DENSITY_XCD_REMAP 1
 #endif
@@ -38,8 +33,7 @@ constexpr int kRounds = 8;
 template <int DM, bool LOCAL>
 __global__ __launch_bounds__(kBlock) void density_kernel(
     const double2* __restrict__ roots, const int32_t* __restrict__ degrees,
-    const uint32_t* __restrict__ status, uint32_t skip_mask, int64_t n, double x0, double y0,
-    double sx, double sy, int width, int height, int32_t* __restrict__ hist,
+    const uint32_t* __restrict__ status, uint32_t skip_mask, int64_t n, BinWindow win,
     const double2* __restrict__ centers, const double* __restrict__ radii, double rmax2)
 {
 #pragma clang fp contract(off)
@@ -59,7 +53,6 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
         d = degrees ? degrees[i] : DM;
         d = d > DM ? DM : d;
     }
-    const double w = (double)width, hgt = (double)height;
     double2 c = make_double2(0.0, 0.0);
     double rho = 0.0;
     if (LOCAL && d > 0) {
@@ -79,30 +72,12 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
                 if (!inside)
                     z = make_double2(__builtin_nan(""), 0.0);
             }
-            const double u = (z.x - x0) * sx;
-            const double v = (z.y - y0) * sy;
-            if (u >= 0.0 && u < w && v >= 0.0 && v < hgt)
-                bin[k] = (int)v * width + (int)u;
+            bin[k] = pixel_of(z.x, z.y, win);
         }
     }
-    const int lane = __lane_id();
 #pragma unroll
-    for (int k = 0; k < DM; ++k) {
-        int b = bin[k];
-        uint64_t pending = __ballot(b >= 0);
-        for (int round = 0; round < kRounds && pending; ++round) {
-            const int leader = __builtin_ctzll(pending);
-            const int lb = __builtin_amdgcn_readlane(b, leader);
-            const uint64_t same = __ballot(b == lb);
-            if (lane == leader)
-                atomicAdd(hist + lb, __builtin_popcountll(same));
-            if (b == lb)
-                b = -1;
-            pending &= ~same;
-        }
-        if (b >= 0)
-            atomicAdd(hist + b, 1);
-    }
+    for (int k = 0; k < DM; ++k)
+        wave_count(bin[k], win.hist);
 }
 
 template <int DM>
@@ -115,14 +90,12 @@ hipError_t launch_dm(const DensityArgs& a, hipStream_t stream)
     if (a.centers)
         hipLaunchKernelGGL((density_kernel<DM, true>), dim3((unsigned)blocks), dim3(kBlock), 0,
                            stream, reinterpret_cast<const double2*>(a.roots), a.degrees,
-                           a.status, a.skip_mask, a.n, a.x0, a.y0, a.sx, a.sy, a.width,
-                           a.height, a.hist, reinterpret_cast<const double2*>(a.centers),
-                           a.radii, a.rmax2);
+                           a.status, a.skip_mask, a.n, a.win,
+                           reinterpret_cast<const double2*>(a.centers), a.radii, a.rmax2);
     else
         hipLaunchKernelGGL((density_kernel<DM, false>), dim3((unsigned)blocks), dim3(kBlock), 0,
                            stream, reinterpret_cast<const double2*>(a.roots), a.degrees,
-                           a.status, a.skip_mask, a.n, a.x0, a.y0, a.sx, a.sy, a.width,
-                           a.height, a.hist, nullptr, nullptr, 0.0);
+                           a.status, a.skip_mask, a.n, a.win, nullptr, nullptr, 0.0);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bin.hpp"
 #include "proots.h"
 
 namespace proots {
@@ -23,6 +24,12 @@ struct SolveArgs {
     double polish_tol;
     int32_t tile;         // > 0 with degrees: persistent degree-bucketed launch
     int32_t grid_blocks;  // persistent launch: number of one-wave blocks (0 = one per tile)
+    // binning epilogue: win.hist == nullptr for none; else every root of a
+    // polynomial whose final status has no bit of skip_mask is counted into
+    // win.hist exactly as the density kernel would count it (roots may then
+    // be nullptr: not stored)
+    BinWindow win;
+    uint32_t skip_mask;
 };
 
 int max_tile();
@@ -36,9 +43,7 @@ struct DensityArgs {
     uint32_t skip_mask;
     int64_t n;
     int32_t dmax;
-    double x0, y0, sx, sy;
-    int32_t width, height;
-    int32_t* hist;
+    BinWindow win;
     // local-coordinate form: root w of polynomial i counts iff |w|^2 < rmax2
     // and is binned at centers[i] + radii[i] * w (centers == nullptr: plain)
     const pr_complex* centers;

@@ -37,6 +37,17 @@
 //   * FP32 form: sweeps in FP32, test in FP64, then every root is polished
 //     by Newton steps r <- r - p(r)/p'(r) in FP64 on the original
 //     coefficients.
+//   * Binning epilogue (Sec. III's roots-to-pixels path, optional): once
+//     the status is final, the wave counts every lane's roots with merged
+//     atomics -- the same decisions and counts as the density kernel over
+//     the stored roots, without a second launch.  The FP32 form bins its
+//     polished roots from registers.  The FP64 form stores each root as it
+//     deflates; it either reads them back at the end (kBinReread: a few
+//     bytes more traffic, no extra registers across the QR loops) or, when
+//     the roots are not stored, keeps one pixel index per deflated root in
+//     registers (kBinKeep).  The matrix's diagonal cannot stand in for the
+//     deflated roots: the identity steps of lanes that ride along preserve
+//     values, not the sign of zeros or entries next to an overflowed one.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -310,6 +321,11 @@ __device__ __forceinline__ cx<double> polish(cx<double> r, const cx<double> (&a)
     return r;
 }
 
+// Binning epilogue variants (template argument of the kernels).
+constexpr int kBinNone = 0;
+constexpr int kBinReread = 1;  // FP64: roots stored, read back for binning
+constexpr int kBinKeep = 2;    // pixel indices kept in registers (roots optional)
+
 // Everything a lane needs to solve one polynomial.
 struct PolyIO {
     const double2* coeffs;
@@ -317,23 +333,32 @@ struct PolyIO {
     const int32_t* degrees;
     int64_t n;
     double2* roots;
+    const double2* roots_again;  // same array, second pointer: kBinReread reads it back
     uint32_t* status;
     int32_t* iters;
     int cap;
     uint32_t flags;
     int polish_steps;
     double polish_tol;
+    BinWindow win;  // binning epilogue only
+    uint32_t skip_mask;
 };
 
 // Solve polynomial i on this lane.  valid == false: the lane has no
 // polynomial this round and only rides along in the wave's level loops.
-// FP32 selects the FP32-sweep + FP64-polish form.  No early return: every
-// lane of the wave reaches the wave-uniform loops.
-template <bool FP32, int DM>
+// FP32 selects the FP32-sweep + FP64-polish form; BIN != kBinNone adds the
+// binning epilogue (kBinKeep lets io.roots be null).  No early return: every
+// lane of the wave reaches the wave-uniform loops and the epilogue's ballots.
+template <bool FP32, int DM, int BIN>
 __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool valid)
 {
     using T = typename std::conditional<FP32, float, double>::type;
     const int64_t n = io.n;
+    const bool store = BIN != kBinKeep || io.roots != nullptr;  // wave-uniform
+    int bins[DM];
+#pragma unroll
+    for (int k = 0; k < DM; ++k)
+        bins[k] = -1;
     const double qnan = __builtin_nan("");
     int d = valid ? (io.degrees ? io.degrees[i] : DM) : 0;
     uint32_t st = 0;
@@ -348,10 +373,11 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
     const bool ok = valid && !st;
     const int dd = ok ? d : 0;  // 0: this lane takes no level
     if (valid) {
+        if (store)
 #pragma unroll
-        for (int k = 0; k < DM; ++k)
-            if (k >= dd)
-                io.roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
+            for (int k = 0; k < DM; ++k)
+                if (k >= dd)
+                    io.roots[(int64_t)k * n + i] = make_double2(qnan, qnan);
         if (io.iters)
 #pragma unroll
             for (int m = 2; m <= DM; ++m)
@@ -370,10 +396,32 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
 
     if constexpr (!FP32) {
         iterate<double, DM>(h, dd, io.cap, exc, fixed, st, io.iters, n, i, [&](int k, cx<double> v) {
-            io.roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
+            if (store)
+                io.roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
+            if constexpr (BIN == kBinKeep) {
+                // k is a compile-time constant after inlining
+                const int b = pixel_of(v.re, v.im, io.win);
+#pragma unroll
+                for (int q = 0; q < DM; ++q)
+                    if (q == k)
+                        bins[q] = b;
+            }
         });
-        if (ok)
-            io.roots[i] = make_double2(h[0][0].re, h[0][0].im);
+        if (ok) {
+            if (store)
+                io.roots[i] = make_double2(h[0][0].re, h[0][0].im);
+            if constexpr (BIN == kBinKeep)
+                bins[0] = pixel_of(h[0][0].re, h[0][0].im, io.win);
+            if constexpr (BIN == kBinReread) {
+                bins[0] = pixel_of(h[0][0].re, h[0][0].im, io.win);
+#pragma unroll
+                for (int k = 1; k < DM; ++k)
+                    if (k < dd) {
+                        const double2 v = io.roots_again[(int64_t)k * n + i];
+                        bins[k] = pixel_of(v.x, v.y, io.win);
+                    }
+            }
+        }
     } else {
         cx<float> e[DM];
 #pragma unroll
@@ -428,12 +476,22 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
                 st |= PR_ST_POLISH_UNCONVERGED;
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                if (k < d)
-                    io.roots[(int64_t)k * n + i] = make_double2(r[k].re, r[k].im);
+                if (k < d) {
+                    if (store)
+                        io.roots[(int64_t)k * n + i] = make_double2(r[k].re, r[k].im);
+                    if constexpr (BIN != kBinNone)
+                        bins[k] = pixel_of(r[k].re, r[k].im, io.win);
+                }
         }
     }
     if (valid)
         io.status[i] = st;
+    if constexpr (BIN != kBinNone) {
+        const bool keep = valid && !(st & io.skip_mask);
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            wave_count(keep ? bins[k] : -1, io.win.hist);
+    }
 }
 
 #ifndef PR_FP64_WAVES
@@ -442,19 +500,22 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
 #ifndef PR_FP32_WAVES
 #define PR_FP32_WAVES 1
 #endif
-template <bool FP32>
+#ifndef PR_FP64_BIN_WAVES
+#define PR_FP64_BIN_WAVES 1
+#endif
+template <bool FP32, int BIN = kBinNone>
 struct WavesPerEU {
-    static constexpr int v = FP32 ? PR_FP32_WAVES : PR_FP64_WAVES;
+    static constexpr int v = FP32 ? PR_FP32_WAVES : (BIN == kBinKeep ? PR_FP64_BIN_WAVES : PR_FP64_WAVES);
 };
 
 // One lane per polynomial in index order (all polynomials of one degree, or
 // no degree array).
-template <bool FP32, int DM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32>::v)))
+template <bool FP32, int DM, int BIN>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32, BIN>::v)))
 void solve_flat_kernel(PolyIO io)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    solve_poly<FP32, DM>(io, i, i < io.n);
+    solve_poly<FP32, DM, BIN>(io, i, i < io.n);
 }
 
 // Mixed degrees, one persistent launch.  Each block is one wave and walks
@@ -468,8 +529,8 @@ void solve_flat_kernel(PolyIO io)
 constexpr int kTileMax = 4096;
 constexpr int kWave = 64;
 
-template <bool FP32, int DM>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32>::v)))
+template <bool FP32, int DM, int BIN>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32, BIN>::v)))
 void solve_tiled_kernel(PolyIO io, int tile)
 {
     __shared__ uint16_t list[kTileMax + (DM + 1) * kWave];
@@ -524,10 +585,27 @@ void solve_tiled_kernel(PolyIO io, int tile)
         for (int s = 0; s < total; s += kWave) {
             const uint16_t e = list[s + lane];
             const bool valid = e != 0xFFFF;
-            solve_poly<FP32, DM>(io, base + (valid ? e : 0), valid);
+            solve_poly<FP32, DM, BIN>(io, base + (valid ? e : 0), valid);
         }
         __syncthreads();
     }
+}
+
+template <bool FP32, int DM, int BIN>
+hipError_t launch_layout(const PolyIO& io, const SolveArgs& a, hipStream_t stream)
+{
+    if (a.degrees && a.tile > 0) {
+        const int tile = a.tile;
+        const int64_t tiles = (a.n + tile - 1) / tile;
+        const int64_t grid = a.grid_blocks > 0 && a.grid_blocks < tiles ? a.grid_blocks : tiles;
+        hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM, BIN>), dim3((unsigned)grid), dim3(kWave),
+                           0, stream, io, tile);
+    } else {
+        const int64_t blocks = (a.n + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((solve_flat_kernel<FP32, DM, BIN>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, stream, io);
+    }
+    return hipGetLastError();
 }
 
 template <bool FP32, int DM>
@@ -539,24 +617,21 @@ hipError_t launch_dm(const SolveArgs& a, hipStream_t stream)
     io.degrees = a.degrees;
     io.n = a.n;
     io.roots = reinterpret_cast<double2*>(a.roots);
+    io.roots_again = io.roots;
     io.status = a.status;
     io.iters = a.iters;
     io.cap = a.cap;
     io.flags = a.flags;
     io.polish_steps = a.polish_steps;
     io.polish_tol = a.polish_tol;
-    if (a.degrees && a.tile > 0) {
-        const int tile = a.tile;
-        const int64_t tiles = (a.n + tile - 1) / tile;
-        const int64_t grid = a.grid_blocks > 0 && a.grid_blocks < tiles ? a.grid_blocks : tiles;
-        hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM>), dim3((unsigned)grid), dim3(kWave), 0,
-                           stream, io, tile);
-    } else {
-        const int64_t blocks = (a.n + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL((solve_flat_kernel<FP32, DM>), dim3((unsigned)blocks), dim3(kBlock), 0,
-                           stream, io);
-    }
-    return hipGetLastError();
+    io.win = a.win;
+    io.skip_mask = a.skip_mask;
+    if (!a.win.hist)
+        return launch_layout<FP32, DM, kBinNone>(io, a, stream);
+    if constexpr (!FP32)
+        if (a.roots)
+            return launch_layout<FP32, DM, kBinReread>(io, a, stream);
+    return launch_layout<FP32, DM, kBinKeep>(io, a, stream);
 }
 
 template <bool FP32>

@@ -101,6 +101,30 @@ def test_density_argument_validation(lib):
     assert call(n=0, roots=None) == pr.PR_OK
 
 
+def test_solve_bin_argument_validation(lib):
+    import paper_2507_02164_amd as pr
+    f = ctypes.c_void_p(0x1000)
+
+    def call(coeffs=f, roots=f, status=f, hist=f, n=4, dmax=6, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0,
+             w=8, h=8, opts=None):
+        return lib.pr_solve_bin(coeffs, None, n, dmax, roots, status, opts, 0, x0, x1, y0, y1, w,
+                                h, hist, None)
+
+    assert call(coeffs=None) == pr.PR_ERR_INVALID_ARG
+    assert call(status=None) == pr.PR_ERR_INVALID_ARG
+    assert call(hist=None) == pr.PR_ERR_INVALID_ARG
+    assert call(n=-1) == pr.PR_ERR_INVALID_ARG
+    assert call(dmax=0) == pr.PR_ERR_INVALID_ARG
+    assert call(x1=-3.0) == pr.PR_ERR_INVALID_ARG
+    assert call(w=0) == pr.PR_ERR_INVALID_ARG
+    assert call(y0=float("nan")) == pr.PR_ERR_INVALID_ARG
+    assert call(opts=ctypes.byref(pr.SolveOpts(precision=9))) == pr.PR_ERR_UNSUPPORTED
+    assert call(opts=ctypes.byref(pr.SolveOpts(polish_steps=20))) == pr.PR_ERR_INVALID_ARG
+    # roots may be NULL (counted, not stored); n == 0 is a no-op
+    assert call(n=0, roots=None) == pr.PR_OK
+    assert call(n=0, coeffs=None, roots=None, status=None) == pr.PR_OK
+
+
 def test_backward_argument_validation(lib):
     import paper_2507_02164_amd as pr
     f = ctypes.c_void_p(0x1000)
