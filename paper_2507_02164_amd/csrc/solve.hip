@@ -106,6 +106,22 @@ __device__ __forceinline__ void rot_cols(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s)
     y.im = c.re * yi + c.im * yr - s.re * xi - s.im * xr;
 }
 
+// Column rotation of the row whose left entry x a rotating lane has just
+// annihilated (x == 0 exactly): (x, y) <- (conj(s) y, c y), 10 operations
+// instead of 16.  A lane that did not rotate has (c, s) = (1, 0) and keeps
+// its x, which need not be zero, by selection.
+template <typename T>
+__device__ __forceinline__ void rot_cols_zero(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s, bool go)
+{
+    T yr = y.re, yi = y.im;
+    const T xr = s.re * yr + s.im * yi;
+    const T xi = s.re * yi - s.im * yr;
+    x.re = pick(go, xr, x.re);
+    x.im = pick(go, xi, x.im);
+    y.re = c.re * yr - c.im * yi;
+    y.im = c.re * yi + c.im * yr;
+}
+
 // One shifted QR step on the leading M x M block (Alg. 1 body via Sec. II-C),
 // executed by every lane of the wave.  Lanes with act == false take the
 // identity rotation (c, s) = (1, 0) and shift 0 throughout, which leaves
@@ -117,12 +133,17 @@ __device__ __forceinline__ void rot_cols(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s)
 template <typename T, int DM, int M>
 __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
 {
+    // the shortened rotation of the annihilated row, inside the loop and at
+    // its end; inside the loop in FP64 it measured 170 VGPRs instead of 160
+    // (one wave per SIMD fewer), so FP64 takes the plain rotation there
+    constexpr bool kZeroInLoop = std::is_same<T, float>::value;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         h[i][i].re -= sh.re;
         h[i][i].im -= sh.im;
     }
     cx<T> cprev, sprev;
+    bool goprev = false;
 #pragma unroll
     for (int r = 1; r < M; ++r) {
         const cx<T> a = h[r - 1][r - 1], b = h[r][r - 1];
@@ -141,17 +162,21 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
             rot_rows(h[r - 1][j], h[r][j], c, s);
         if (r >= 2) {
             // lagged column rotation r-1 on rows 0..r-1 (row r-1 enters with
-            // h[r-1][r-2] == 0 for acting lanes)
+            // h[r-1][r-2] == 0 for lanes that took row rotation r-1)
 #pragma unroll
-            for (int j = 0; j <= r - 1; ++j)
+            for (int j = 0; j < (kZeroInLoop ? r - 1 : r); ++j)
                 rot_cols(h[j][r - 2], h[j][r - 1], cprev, sprev);
+            if (kZeroInLoop)
+                rot_cols_zero(h[r - 1][r - 2], h[r - 1][r - 1], cprev, sprev, goprev);
         }
         cprev = c;
         sprev = s;
+        goprev = go;
     }
 #pragma unroll
-    for (int j = 0; j <= M - 1; ++j)
+    for (int j = 0; j < M - 1; ++j)
         rot_cols(h[j][M - 2], h[j][M - 1], cprev, sprev);
+    rot_cols_zero(h[M - 1][M - 2], h[M - 1][M - 1], cprev, sprev, goprev);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         h[i][i].re += sh.re;
