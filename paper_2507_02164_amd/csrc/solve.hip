@@ -122,6 +122,19 @@ __device__ __forceinline__ void rot_cols_zero(cx<T>& x, cx<T>& y, cx<T> c, cx<T>
     y.im = c.re * yi + c.im * yr;
 }
 
+// The same inside the row loop, where y is also known: row rotation r has
+// just made it the real rho (or left a zero pair alone), so for a lane with
+// go = true (x, y) <- (conj(s) rho, c rho) takes 4 multiplies and 3 selects.
+template <typename T>
+__device__ __forceinline__ void rot_cols_zero_real(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s, bool go)
+{
+    const T yr = y.re;
+    x.re = pick(go, s.re * yr, x.re);
+    x.im = pick(go, -s.im * yr, x.im);
+    y.im = pick(go, c.im * yr, y.im);
+    y.re = c.re * yr;  // (c, s) = (1, 0) when go is false
+}
+
 // One shifted QR step on the leading M x M block (Alg. 1 body via Sec. II-C),
 // executed by every lane of the wave.  Lanes with act == false take the
 // identity rotation (c, s) = (1, 0) and shift 0 throughout, which leaves
@@ -167,7 +180,7 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
             for (int j = 0; j < (kZeroInLoop ? r - 1 : r); ++j)
                 rot_cols(h[j][r - 2], h[j][r - 1], cprev, sprev);
             if (kZeroInLoop)
-                rot_cols_zero(h[r - 1][r - 2], h[r - 1][r - 1], cprev, sprev, goprev);
+                rot_cols_zero_real(h[r - 1][r - 2], h[r - 1][r - 1], cprev, sprev, goprev);
         }
         cprev = c;
         sprev = s;
