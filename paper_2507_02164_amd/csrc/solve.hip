@@ -67,14 +67,31 @@ constexpr int kBlock = PR_SOLVE_BLOCK;
 // (c, s) = (conj a, conj b) / rho, rho = sqrt(|a|^2 + |b|^2): the only pair
 // for which the Sec. II-C rotation maps (a, b) to (rho, 0).  Computed
 // branch-free (a branch here would split the fully unrolled QR step into
-// basic blocks and stretch register lifetimes across them).  rho == 0 (a and
-// b both zero) is handled by the caller, which then applies the identity --
-// the two entries are already (rho, 0) = (0, 0).  The price of branch-free
-// code is the range: |a|^2 + |b|^2 must not overflow (entries below about
-// 1e154 in FP64, 1e19 in FP32), otherwise NaN propagates and the level ends
-// NOT_CONVERGED.
-__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
-__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+// basic blocks and stretch register lifetimes across them).  A pair whose
+// |a|^2 + |b|^2 is zero -- or, in FP32, below the smallest normal number
+// (both entries under about 1e-19) -- gets the identity instead (the
+// caller's `go` mask): the identity is unitary too, so the eigenvalues are
+// untouched and only that lane's step is skipped.  This lets FP32 use the
+// hardware reciprocal square root directly (it is accurate to 1 ulp on
+// normal inputs; the library routine adds a rescaling for subnormal ones).
+// The price of branch-free code is the range: |a|^2 + |b|^2 must not
+// overflow (entries below about 1e154 in FP64, 1e19 in FP32), otherwise NaN
+// propagates and the level ends NOT_CONVERGED.
+// FP64: the hardware estimate y0 refined once by the third-order series
+// 1/sqrt(x) = y0 (1 - e)^(-1/2) = y0 (1 + e/2 + 3e^2/8 + ...), e = 1 - x y0^2,
+// which takes its relative error eps to about 5 eps^3 / 16 (the estimate's
+// eps measured at most 2^-24.2 on gfx950 over the whole normal range; the
+// refined value is within 0.99 ulp, as the library routine); x must be
+// positive and finite, which the `go` mask guarantees for every value used.
+__device__ __forceinline__ double rsqrt_t(double x)
+{
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double e = __builtin_fma(-x * y0, y0, 1.0);
+    return __builtin_fma(y0 * e, __builtin_fma(e, 0.375, 0.5), y0);
+}
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ bool rotates(double n2) { return n2 > 0.0; }
+__device__ __forceinline__ bool rotates(float n2) { return n2 >= 0x1p-126f; }
 
 // Scalar select on values already computed (a conditional operator on a
 // struct, or on an expression, may be emitted as a branch).
@@ -106,20 +123,36 @@ __device__ __forceinline__ void rot_cols(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s)
     y.im = c.re * yi + c.im * yr - s.re * xi - s.im * xr;
 }
 
+// rot_cols whose x is a diagonal entry receiving its last update of the QR
+// step: the shift d is added back inside the same multiply-add chain
+// (A <- RQ + sI without a separate pass over the diagonal).
+template <typename T>
+__device__ __forceinline__ void rot_cols_diag(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s, cx<T> d)
+{
+    T xr = x.re, xi = x.im, yr = y.re, yi = y.im;
+    x.re = d.re + c.re * xr + c.im * xi + s.re * yr + s.im * yi;
+    x.im = d.im + c.re * xi - c.im * xr + s.re * yi - s.im * yr;
+    y.re = c.re * yr - c.im * yi - s.re * xr + s.im * xi;
+    y.im = c.re * yi + c.im * yr - s.re * xi - s.im * xr;
+}
+
 // Column rotation of the row whose left entry x a rotating lane has just
 // annihilated (x == 0 exactly): (x, y) <- (conj(s) y, c y), 10 operations
 // instead of 16.  A lane that did not rotate has (c, s) = (1, 0) and keeps
-// its x, which need not be zero, by selection.
+// its x, which need not be zero, by selection.  Used for the bottom row of
+// the last column rotation, whose y is the last diagonal entry: the shift d
+// is added back in the same chain.
 template <typename T>
-__device__ __forceinline__ void rot_cols_zero(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s, bool go)
+__device__ __forceinline__ void rot_cols_zero(cx<T>& x, cx<T>& y, cx<T> c, cx<T> s, bool go,
+                                              cx<T> d)
 {
     T yr = y.re, yi = y.im;
     const T xr = s.re * yr + s.im * yi;
     const T xi = s.re * yi - s.im * yr;
     x.re = pick(go, xr, x.re);
     x.im = pick(go, xi, x.im);
-    y.re = c.re * yr - c.im * yi;
-    y.im = c.re * yi + c.im * yr;
+    y.re = d.re + c.re * yr - c.im * yi;
+    y.im = d.im + c.re * yi + c.im * yr;
 }
 
 // The same inside the row loop, where y is also known: row rotation r has
@@ -138,8 +171,8 @@ __device__ __forceinline__ void rot_cols_zero_real(cx<T>& x, cx<T>& y, cx<T> c, 
 // One shifted QR step on the leading M x M block (Alg. 1 body via Sec. II-C),
 // executed by every lane of the wave.  Lanes with act == false take the
 // identity rotation (c, s) = (1, 0) and shift 0 throughout, which leaves
-// their matrix unchanged bit for bit (1*x + 0*y == x); the entries a real
-// rotation overwrites are selected.  Running the step wave-uniformly, with no
+// the values of their matrix unchanged (1*x + 0*y == x for finite y; a zero
+// may change sign); the entries a real rotation overwrites are selected.  Running the step wave-uniformly, with no
 // lane-divergent branch around it, matters: a divergent branch would keep
 // the pre-step matrix of the lanes that skip it alive next to the post-step
 // matrix of the lanes that take it, doubling the register footprint.
@@ -162,9 +195,10 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
         const cx<T> a = h[r - 1][r - 1], b = h[r][r - 1];
         const T n2 = a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im;
         const T inv = rsqrt_t(n2);
-        // a lane rotates only if it acts this trip and (a, b) != 0 (NaN
-        // fails n2 > 0 too); otherwise (c, s) = (1, 0) and both entries stay
-        const bool go = act && n2 > T(0);
+        // a lane rotates only if it acts this trip and (a, b) is not
+        // (numerically) zero -- NaN fails the test too; otherwise
+        // (c, s) = (1, 0) and both entries stay
+        const bool go = act && rotates(n2);
         const cx<T> c = {pick(go, a.re * inv, T(1)), pick(go, -a.im * inv, T(0))};
         const cx<T> s = {pick(go, b.re * inv, T(0)), pick(go, -b.im * inv, T(0))};
         // the rotation maps (h[r-1][r-1], h[r][r-1]) to (rho, 0)
@@ -177,8 +211,12 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
             // lagged column rotation r-1 on rows 0..r-1 (row r-1 enters with
             // h[r-1][r-2] == 0 for lanes that took row rotation r-1)
 #pragma unroll
-            for (int j = 0; j < (kZeroInLoop ? r - 1 : r); ++j)
-                rot_cols(h[j][r - 2], h[j][r - 1], cprev, sprev);
+            for (int j = 0; j < (kZeroInLoop ? r - 1 : r); ++j) {
+                if (j == r - 2)  // h[r-2][r-2] takes its last update: add the shift back
+                    rot_cols_diag(h[j][r - 2], h[j][r - 1], cprev, sprev, sh);
+                else
+                    rot_cols(h[j][r - 2], h[j][r - 1], cprev, sprev);
+            }
             if (kZeroInLoop)
                 rot_cols_zero_real(h[r - 1][r - 2], h[r - 1][r - 1], cprev, sprev, goprev);
         }
@@ -187,14 +225,11 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
         goprev = go;
     }
 #pragma unroll
-    for (int j = 0; j < M - 1; ++j)
+    for (int j = 0; j < M - 2; ++j)
         rot_cols(h[j][M - 2], h[j][M - 1], cprev, sprev);
-    rot_cols_zero(h[M - 1][M - 2], h[M - 1][M - 1], cprev, sprev, goprev);
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        h[i][i].re += sh.re;
-        h[i][i].im += sh.im;
-    }
+    rot_cols_diag(h[M - 2][M - 2], h[M - 2][M - 1], cprev, sprev, sh);
+    rot_cols_zero(h[M - 1][M - 2], h[M - 1][M - 1], cprev, sprev, goprev, sh);
+    // every diagonal entry got the shift back in its last update above
 }
 
 template <typename T>
