@@ -176,8 +176,8 @@ def bench_l2fit(args, torch, pr, dev, n=1 << 21, degree=6, nr=8, nt=16):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--grid", type=int, default=4096, help="grid side; n = grid^2")
     ap.add_argument("--workload", choices=["parametric", "mixed"], default="parametric",
                     help="parametric: the default timed workload; mixed: 64M polynomials of "
@@ -265,6 +265,7 @@ def main():
         fused_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evf]))
         back_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evf]))
         res[form] = dict(step_ms=step_ms, solve_bin_ms=fused_ms, backward_ms=back_ms,
+                         solve_bin_ms_each=[round(e[0].elapsed_time(e[1]), 4) for e in evf],
                          polys_per_s=n / (step_ms * 1e-3),
                          alg_flops_per_poly=flops / n,
                          mean_qr_steps=float(its_h.sum(axis=0).mean()),

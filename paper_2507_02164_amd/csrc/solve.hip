@@ -368,30 +368,66 @@ __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs
 }
 
 // Newton polish in FP64 on the original coefficients a (zeros above the
-// degree, so Horner from DM gives the same value as from the degree).
-template <int DM>
-__device__ __forceinline__ cx<double> polish(cx<double> r, const cx<double> (&a)[DM + 1],
-                                             int steps, double& last2)
+// degree, so Horner from DM gives the same value as from the degree):
+// r <- r - p(r) / p'(r), a step skipped where p'(r) is zero or not finite.
+// The roots K0..K0+G-1 are polished together: their Horner recurrences are
+// independent, and interleaving them hides the FP64 multiply-add latency
+// that a single chain would wait on.  The step needs 1/|p'|^2 only to the
+// accuracy of a correction: the hardware reciprocal estimate refined once
+// (relative error about 2^-48) instead of a correctly rounded division.
+// last2 receives |last step|^2.
+#ifndef PR_POLISH_GROUP
+#define PR_POLISH_GROUP 2
+#endif
+template <int DM, int K0, int G>
+__device__ __forceinline__ void polish_group(cx<double> (&r)[DM], const cx<double> (&a)[DM + 1],
+                                             int steps, double (&last2)[DM])
 {
-    last2 = 0.0;
-    for (int s = 0; s < steps; ++s) {
-        cx<double> p = a[DM], dp = {0.0, 0.0};
 #pragma unroll
-        for (int k = DM - 1; k >= 0; --k) {
-            dp = dp * r + p;
-            p = p * r + a[k];
+    for (int g = K0; g < K0 + G; ++g)
+        last2[g] = 0.0;
+    for (int s = 0; s < steps; ++s) {
+        cx<double> p[G], dp[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            p[g] = a[DM];
+            dp[g] = {0.0, 0.0};
         }
-        double den = norm2(dp);
-        cx<double> delta = {0.0, 0.0};
-        if (den > 0.0 && isfinite(den)) {
-            cx<double> q = p * conj(dp);
-            double inv = 1.0 / den;
-            delta = {q.re * inv, q.im * inv};
+#pragma unroll
+        for (int k = DM - 1; k >= 0; --k)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                dp[g] = dp[g] * r[K0 + g] + p[g];
+                p[g] = p[g] * r[K0 + g] + a[k];
+            }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const double den = norm2(dp[g]);
+            cx<double> delta = {0.0, 0.0};
+            if (den >= 0x1p-1022 && isfinite(den)) {
+                const cx<double> q = p[g] * conj(dp[g]);
+                const double y0 = __builtin_amdgcn_rcp(den);
+                const double inv = __builtin_fma(y0, __builtin_fma(-den, y0, 1.0), y0);
+                delta = {q.re * inv, q.im * inv};
+            }
+            r[K0 + g] = r[K0 + g] - delta;
+            last2[K0 + g] = norm2(delta);
         }
-        r = r - delta;
-        last2 = norm2(delta);
     }
-    return r;
+}
+
+// All groups of roots below the lane's degree d; a group that no lane of
+// the wave needs (degrees below K0 across the wave) is skipped.
+template <int DM, int K0>
+__device__ __forceinline__ void polish_all(cx<double> (&r)[DM], const cx<double> (&a)[DM + 1],
+                                           int steps, double (&last2)[DM], int d)
+{
+    if constexpr (K0 < DM) {
+        constexpr int G = (DM - K0) < PR_POLISH_GROUP ? (DM - K0) : PR_POLISH_GROUP;
+        if (__ballot(K0 < d))
+            polish_group<DM, K0, G>(r, a, steps, last2);
+        polish_all<DM, K0 + G>(r, a, steps, last2, d);
+    }
 }
 
 // Binning epilogue variants (template argument of the kernels).
@@ -521,17 +557,20 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
                 }
             }
             cx<double> r[DM];
+            double last2[DM];
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                r[k] = {(double)e[k].re, (double)e[k].im};
+            polish_all<DM, 0>(r, a, io.polish_steps, last2, d);
             const double tol2 = io.polish_tol * io.polish_tol;
             bool bad = false;
 #pragma unroll
             for (int k = 0; k < DM; ++k) {
-                r[k] = {qnan, qnan};
                 if (k < d) {
-                    double last2;
-                    r[k] = polish<DM>(cx<double>{(double)e[k].re, (double)e[k].im}, a,
-                                      io.polish_steps, last2);
-                    if (!(last2 <= tol2 * norm2(r[k])))
+                    if (!(last2[k] <= tol2 * norm2(r[k])))
                         bad = true;
+                } else {
+                    r[k] = {qnan, qnan};
                 }
             }
             // Two polished roots on top of each other: one root was lost.
