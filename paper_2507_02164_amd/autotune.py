@@ -30,7 +30,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tuning", "tune_cache.json")
 
 TILES = (512, 1024, 2048, 4096)
-BLOCKS_PER_CU = (8, 16, 32, 64)
+BLOCKS_PER_CU = (8, 16, 32, 64, 128)
 CAPS = (20, 24, 30)
 
 _cache = None
