@@ -3,9 +3,10 @@ HIP graph and replayed.
 
 Every launch the library makes is a plain kernel launch on the caller's
 stream (no memset nodes: the image is cleared by a fill kernel), so the
-three calls capture into one graph whose replay re-runs them on whatever the
-captured buffers hold.  To solve a new batch of the same shape, copy it into
-``coeffs`` (and ``degrees`` / ``cotangents``) and replay.
+calls capture into one graph whose replay re-runs them on whatever the
+captured buffers hold.  With ``fused`` (the default) solve and density are
+one launch (pr_solve_bin); otherwise two.  To solve a new batch of the same
+shape, copy it into ``coeffs`` (and ``degrees`` / ``cotangents``) and replay.
 """
 from __future__ import annotations
 
@@ -16,7 +17,7 @@ from . import _capi
 
 class PathGraph:
     def __init__(self, coeffs, degrees=None, precision="fp32_polish", window=None, shape=None,
-                 cotangents=None, skip_mask=0, **solve_opts):
+                 cotangents=None, skip_mask=0, fused=True, **solve_opts):
         self.coeffs = coeffs
         self.degrees = degrees
         self.precision = precision
@@ -24,6 +25,7 @@ class PathGraph:
         self.shape = shape
         self.cotangents = cotangents
         self.skip_mask = skip_mask
+        self.fused = fused
         self.solve_opts = solve_opts
         dmax = coeffs.shape[0] - 1
         n = coeffs.shape[1]
@@ -47,9 +49,15 @@ class PathGraph:
             self._step()
 
     def _step(self):
-        _capi.solve(self.coeffs, self.degrees, self.precision, roots=self.roots,
-                    status=self.status, **self.solve_opts)
-        if self.hist is not None:
+        if self.hist is not None and self.fused:
+            self.hist.zero_()
+            _capi.solve_bin(self.coeffs, self.window, self.shape, self.degrees, self.precision,
+                            skip_mask=self.skip_mask, out=self.hist, roots=self.roots,
+                            status=self.status, **self.solve_opts)
+        else:
+            _capi.solve(self.coeffs, self.degrees, self.precision, roots=self.roots,
+                        status=self.status, **self.solve_opts)
+        if self.hist is not None and not self.fused:
             self.hist.zero_()
             _capi.density(self.roots, self.window, self.shape, self.degrees, self.status,
                           self.skip_mask, out=self.hist)

@@ -22,9 +22,10 @@ def _eager(c, d, prec, win, shape, cot):
     return [to_host(x) for x in (r, st2, h, g)]
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("precision", ["fp32_polish", "fp64"])
 @pytest.mark.parametrize("mixed", [False, True])
-def test_graph_replay_matches_eager(precision, mixed):
+def test_graph_replay_matches_eager(precision, mixed, fused):
     from paper_2507_02164_amd.graph import PathGraph
     n = 50000
     if mixed:
@@ -37,7 +38,7 @@ def test_graph_replay_matches_eager(precision, mixed):
     c = to_dev(a)
     cot = to_dev(workloads.cotangents(n, seed=2))
     want = _eager(c, d, precision, win, shape, cot)
-    g = PathGraph(c, d, precision, win, shape, cot)
+    g = PathGraph(c, d, precision, win, shape, cot, fused=fused)
     for rep in range(3):
         g.replay()
         torch.cuda.synchronize()
