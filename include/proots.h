@@ -63,8 +63,11 @@ enum pr_status_bits {
     PR_ST_NOT_CONVERGED = 1u << 3,     /* a level hit the iteration cap and was deflated anyway */
     PR_ST_POLISH_UNCONVERGED = 1u << 4,/* FP32 form: a Newton polish did not settle, or two
                                           polished roots coincide */
-    PR_ST_SINGULAR_DERIV = 1u << 5     /* backward: p'(r) zero or non-finite at some root; that
+    PR_ST_SINGULAR_DERIV = 1u << 5,    /* backward: p'(r) zero or non-finite at some root; that
                                           root contributed nothing */
+    PR_ST_RESOLVED_FP64 = 1u << 6      /* FP32 form with PR_FLAG_FP64_FALLBACK: the FP32 result
+                                          was flagged, the polynomial was solved again in FP64,
+                                          and its roots and other bits are the FP64 solve's */
 };
 
 /* Arithmetic of the QR sweeps. */
@@ -78,10 +81,17 @@ typedef enum pr_precision {
 enum pr_solve_flags {
     PR_FLAG_NO_EXCEPTIONAL_SHIFT = 1u << 0, /* debug: pure Rayleigh shift only (a polynomial
                                                such as z^d - c then stalls to the cap) */
-    PR_FLAG_FIXED_STEPS = 1u << 1           /* Alg. 2 literally: every level takes exactly
+    PR_FLAG_FIXED_STEPS = 1u << 1,          /* Alg. 2 literally: every level takes exactly
                                                max_iter_per_level QR steps with the pure
                                                Rayleigh shift, no convergence test and no
                                                exceptional shift; NOT_CONVERGED is never set */
+    PR_FLAG_FP64_FALLBACK = 1u << 2         /* FP32 form: every polynomial whose FP32 result
+                                               ends NOT_CONVERGED or POLISH_UNCONVERGED is
+                                               solved again by the FP64 form (a second launch
+                                               on the same stream that reads the status array
+                                               and solves only those); its roots, status (with
+                                               PR_ST_RESOLVED_FP64) and iteration counts are
+                                               then the FP64 solve's.  No effect on PR_FP64 */
 };
 
 /* Options of pr_solve.  Zero-initialised = defaults. */

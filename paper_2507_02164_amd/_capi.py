@@ -25,6 +25,7 @@ ST_ZERO_LEADING = 1 << 2
 ST_NOT_CONVERGED = 1 << 3
 ST_POLISH_UNCONVERGED = 1 << 4
 ST_SINGULAR_DERIV = 1 << 5
+ST_RESOLVED_FP64 = 1 << 6
 
 FP64 = 0
 FP32_POLISH = 1
@@ -32,6 +33,7 @@ PRECISIONS = {"fp64": FP64, "fp32_polish": FP32_POLISH}
 
 FLAG_NO_EXCEPTIONAL_SHIFT = 1 << 0
 FLAG_FIXED_STEPS = 1 << 1
+FLAG_FP64_FALLBACK = 1 << 2
 
 
 class ProotsError(RuntimeError):

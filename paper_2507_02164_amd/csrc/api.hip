@@ -87,7 +87,8 @@ static int solve_common(const pr_complex* coeffs, const int32_t* degrees, int64_
         return PR_ERR_INVALID_ARG;
     if (!(o.polish_tol >= 0.0 && o.polish_tol < 1.0))
         return PR_ERR_INVALID_ARG;
-    if (o.flags & ~(uint32_t)(PR_FLAG_NO_EXCEPTIONAL_SHIFT | PR_FLAG_FIXED_STEPS))
+    if (o.flags &
+        ~(uint32_t)(PR_FLAG_NO_EXCEPTIONAL_SHIFT | PR_FLAG_FIXED_STEPS | PR_FLAG_FP64_FALLBACK))
         return PR_ERR_UNSUPPORTED;
     if (o.tile < -1 || o.tile > max_tile() || o.grid_blocks < 0)
         return PR_ERR_INVALID_ARG;
@@ -113,6 +114,8 @@ static int solve_common(const pr_complex* coeffs, const int32_t* degrees, int64_
         a.grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : kDefaultBlocksPerCU * cu_count();
     a.win = win ? *win : BinWindow{0.0, 0.0, 0.0, 0.0, 0, 0, nullptr};
     a.skip_mask = skip_mask;
+    a.fallback_tile = a.tile > 0 ? a.tile : kDefaultTile;
+    a.fallback_grid = o.grid_blocks > 0 ? o.grid_blocks : kDefaultBlocksPerCU * cu_count();
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (o.precision == PR_FP64)
         return hip_status(launch_solve_fp64(a, s));

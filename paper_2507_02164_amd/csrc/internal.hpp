@@ -30,6 +30,9 @@ struct SolveArgs {
     // be nullptr: not stored)
     BinWindow win;
     uint32_t skip_mask;
+    // PR_FLAG_FP64_FALLBACK (FP32 form): layout of the second, FP64 launch
+    int32_t fallback_tile;
+    int32_t fallback_grid;
 };
 
 int max_tile();

@@ -451,7 +451,13 @@ struct PolyIO {
     double polish_tol;
     BinWindow win;  // binning epilogue only
     uint32_t skip_mask;
+    uint32_t status_or;   // or-ed into every status written (the FP64 fallback's mark)
+    uint32_t defer_mask;  // binning: polynomials whose status has one of these bits are left
+                          // to the FP64 fallback launch, which bins them after solving again
 };
+
+// Status bits that send an FP32 result to the FP64 fallback.
+constexpr uint32_t kFallbackBits = PR_ST_NOT_CONVERGED | PR_ST_POLISH_UNCONVERGED;
 
 // Solve polynomial i on this lane.  valid == false: the lane has no
 // polynomial this round and only rides along in the wave's level loops.
@@ -596,10 +602,11 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
                 }
         }
     }
+    st |= io.status_or;
     if (valid)
         io.status[i] = st;
     if constexpr (BIN != kBinNone) {
-        const bool keep = valid && !(st & io.skip_mask);
+        const bool keep = valid && !(st & (io.skip_mask | io.defer_mask));
 #pragma unroll
         for (int k = 0; k < DM; ++k)
             wave_count(keep ? bins[k] : -1, io.win.hist);
@@ -637,14 +644,25 @@ void solve_flat_kernel(PolyIO io)
 // every degree bucket is padded to a multiple of 64, then solves the list 64
 // entries at a time: each slice holds one degree, so no lane idles through
 // levels above its degree.  The gathers stay inside the tile, which the
-// caches hold.
+// caches hold.  SELECT (the FP64 fallback): only polynomials whose status
+// has a kFallbackBits bit enter the list, so a sparse selection costs little
+// more than reading the status array.
 constexpr int kTileMax = 4096;
 constexpr int kWave = 64;
 
-template <bool FP32, int DM, int BIN>
+template <bool FP32, int DM, int BIN, bool SELECT>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32, BIN>::v)))
 void solve_tiled_kernel(PolyIO io, int tile)
 {
+    // bucket of tile entry t: its degree (0 = invalid degree), or -1 when
+    // the entry is not part of this launch's list
+    auto bucket = [&](int64_t g) -> int {
+        if constexpr (SELECT)
+            if (!(io.status[g] & kFallbackBits))
+                return -1;
+        const int d = io.degrees ? io.degrees[g] : DM;
+        return (d >= 1 && d <= DM) ? d : 0;
+    };
     __shared__ uint16_t list[kTileMax + (DM + 1) * kWave];
     const int lane = threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this lane
@@ -658,11 +676,7 @@ void solve_tiled_kernel(PolyIO io, int tile)
             count[b] = 0;
         for (int t0 = 0; t0 < cnt_t; t0 += kWave) {
             const int t = t0 + lane;
-            int bk = -1;
-            if (t < cnt_t) {
-                const int d = io.degrees[base + t];
-                bk = (d >= 1 && d <= DM) ? d : 0;
-            }
+            const int bk = t < cnt_t ? bucket(base + t) : -1;
 #pragma unroll
             for (int b = 0; b <= DM; ++b)
                 count[b] += __builtin_popcountll(__ballot(bk == b));
@@ -680,11 +694,7 @@ void solve_tiled_kernel(PolyIO io, int tile)
         // pass 2: scatter tile-local indices into their buckets
         for (int t0 = 0; t0 < cnt_t; t0 += kWave) {
             const int t = t0 + lane;
-            int bk = -1;
-            if (t < cnt_t) {
-                const int d = io.degrees[base + t];
-                bk = (d >= 1 && d <= DM) ? d : 0;
-            }
+            const int bk = t < cnt_t ? bucket(base + t) : -1;
 #pragma unroll
             for (int b = 0; b <= DM; ++b) {
                 const uint64_t m = __ballot(bk == b);
@@ -710,8 +720,8 @@ hipError_t launch_layout(const PolyIO& io, const SolveArgs& a, hipStream_t strea
         const int tile = a.tile;
         const int64_t tiles = (a.n + tile - 1) / tile;
         const int64_t grid = a.grid_blocks > 0 && a.grid_blocks < tiles ? a.grid_blocks : tiles;
-        hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM, BIN>), dim3((unsigned)grid), dim3(kWave),
-                           0, stream, io, tile);
+        hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM, BIN, false>), dim3((unsigned)grid),
+                           dim3(kWave), 0, stream, io, tile);
     } else {
         const int64_t blocks = (a.n + kBlock - 1) / kBlock;
         hipLaunchKernelGGL((solve_flat_kernel<FP32, DM, BIN>), dim3((unsigned)blocks),
@@ -738,12 +748,35 @@ hipError_t launch_dm(const SolveArgs& a, hipStream_t stream)
     io.polish_tol = a.polish_tol;
     io.win = a.win;
     io.skip_mask = a.skip_mask;
+    io.status_or = 0;
+    const bool fallback = FP32 && (a.flags & PR_FLAG_FP64_FALLBACK);
+    io.defer_mask = fallback ? kFallbackBits : 0;
+    hipError_t e;
     if (!a.win.hist)
-        return launch_layout<FP32, DM, kBinNone>(io, a, stream);
-    if constexpr (!FP32)
-        if (a.roots)
-            return launch_layout<FP32, DM, kBinReread>(io, a, stream);
-    return launch_layout<FP32, DM, kBinKeep>(io, a, stream);
+        e = launch_layout<FP32, DM, kBinNone>(io, a, stream);
+    else if (!FP32 && a.roots)
+        e = launch_layout<FP32, DM, FP32 ? kBinKeep : kBinReread>(io, a, stream);
+    else
+        e = launch_layout<FP32, DM, kBinKeep>(io, a, stream);
+    if (e != hipSuccess || !fallback)
+        return e;
+    // FP64 fallback: a second launch over the polynomials the first one
+    // flagged, in tiles, with the same options; it bins what it solves
+    io.status_or = PR_ST_RESOLVED_FP64;
+    io.defer_mask = 0;
+    const int tile = a.fallback_tile;
+    const int64_t tiles = (a.n + tile - 1) / tile;
+    const int64_t grid = a.fallback_grid < tiles ? a.fallback_grid : tiles;
+    if (!a.win.hist)
+        hipLaunchKernelGGL((solve_tiled_kernel<false, DM, kBinNone, true>), dim3((unsigned)grid),
+                           dim3(kWave), 0, stream, io, tile);
+    else if (a.roots)
+        hipLaunchKernelGGL((solve_tiled_kernel<false, DM, kBinReread, true>),
+                           dim3((unsigned)grid), dim3(kWave), 0, stream, io, tile);
+    else
+        hipLaunchKernelGGL((solve_tiled_kernel<false, DM, kBinKeep, true>), dim3((unsigned)grid),
+                           dim3(kWave), 0, stream, io, tile);
+    return hipGetLastError();
 }
 
 template <bool FP32>

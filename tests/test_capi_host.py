@@ -73,6 +73,10 @@ def test_solve_argument_validation(lib):
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_INVALID_ARG
     bad = pr.SolveOpts(flags=0x80)
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
+    bad = pr.SolveOpts(flags=0x8)
+    assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
+    fb = pr.SolveOpts(precision=pr.FP32_POLISH, flags=pr.FLAG_FP64_FALLBACK | pr.FLAG_FIXED_STEPS)
+    assert lib.pr_solve(fake, None, 0, 6, fake, fake, ctypes.byref(fb), None) == pr.PR_OK
     # n == 0 is a valid no-op: nothing is enqueued, the arrays may be NULL
     assert lib.pr_solve(fake, None, 0, 6, fake, fake, ctypes.byref(opts), None) == pr.PR_OK
     assert lib.pr_solve(None, None, 0, 6, None, None, None, None) == pr.PR_OK
