@@ -33,8 +33,7 @@ if ROOT not in sys.path:
 # the shift), and polish FLOPs per root per Newton step at degree d.
 F_LEVEL = {2: 131, 3: 314, 4: 553, 5: 848, 6: 1199}
 PEAK_FP64 = 78.6e12          # MI355X vector FP64, FLOP/s
-PEAK_FP32 = 157.3e12         # MI355X vector FP32 (published; needs packed FP32)
-PEAK_FP32_NONPACKED = 78.6e12
+PEAK_FP32 = 157.3e12         # MI355X vector FP32 (published)
 PEAK_HBM = 8.0e12            # B/s
 
 
@@ -345,9 +344,6 @@ def main():
         out["solve_ratio_fp32polish_over_fp64"] = (res["fp64"]["solve_bin_ms"] /
                                                    res["fp32_polish"]["solve_bin_ms"])
         out["step_ratio_fp32polish_over_fp64"] = res["fp64"]["step_ms"] / res["fp32_polish"]["step_ms"]
-    if main_form == "fp32_polish":
-        out["roofline"]["peak_nonpacked"] = PEAK_FP32_NONPACKED / 1e12
-        out["roofline"]["frac_nonpacked"] = achieved / PEAK_FP32_NONPACKED
     if args.profile_only is None:
         # paper-literal mode (Alg. 2): exactly T = 10 QR steps per level, FP32
         # sweeps as in the paper's implementations; reported as context
