@@ -19,32 +19,6 @@ namespace proots {
 namespace {
 
 constexpr int kBlock = 256;
-#ifndef PR_BACKWARD_NT
-#define PR_BACKWARD_NT 0
-#endif
-
-// Streaming accesses: every byte is touched once, so keep it out of the caches.
-typedef double dvec2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ double2 ld(const double2* p)
-{
-#if PR_BACKWARD_NT
-    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
-    return make_double2(v.x, v.y);
-#else
-    return *p;
-#endif
-}
-
-__device__ __forceinline__ void st2(double2* p, double2 v)
-{
-#if PR_BACKWARD_NT
-    dvec2 w = {v.x, v.y};
-    __builtin_nontemporal_store(w, reinterpret_cast<dvec2*>(p));
-#else
-    *p = v;
-#endif
-}
 
 template <int DM>
 __global__ __launch_bounds__(kBlock) void backward_kernel(
@@ -70,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
         for (int k = 0; k <= DM; ++k) {
             a[k] = {0.0, 0.0};
             if (k <= d) {
-                double2 v = ld(coeffs + (int64_t)k * n + i);
+                double2 v = coeffs[(int64_t)k * n + i];
                 a[k] = {v.x, v.y};
             }
         }
@@ -78,8 +52,8 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
         for (int j = 0; j < DM; ++j) {
             r[j] = gr[j] = {0.0, 0.0};
             if (j < d) {
-                const double2 rv = ld(roots + (int64_t)j * n + i);
-                const double2 gv = ld(grad_roots + (int64_t)j * n + i);
+                const double2 rv = roots[(int64_t)j * n + i];
+                const double2 gv = grad_roots[(int64_t)j * n + i];
                 r[j] = {rv.x, rv.y};
                 gr[j] = {gv.x, gv.y};
             }
@@ -110,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
     }
 #pragma unroll
     for (int k = 0; k <= DM; ++k)
-        st2(grad_coeffs + (int64_t)k * n + i, make_double2(g[k].re, g[k].im));
+        grad_coeffs[(int64_t)k * n + i] = make_double2(g[k].re, g[k].im);
     status[i] = st;
 }
 

@@ -58,10 +58,9 @@
 namespace proots {
 namespace {
 
-#ifndef PR_SOLVE_BLOCK
-#define PR_SOLVE_BLOCK 64
-#endif
-constexpr int kBlock = PR_SOLVE_BLOCK;
+// One-wave blocks: a finished wave's slot refills at once (256-lane blocks
+// measured 6% slower).
+constexpr int kBlock = 64;
 
 // ---------------------------------------------------------------- Givens
 // (c, s) = (conj a, conj b) / rho, rho = sqrt(|a|^2 + |b|^2): the only pair
@@ -376,9 +375,7 @@ __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs
 // accuracy of a correction: the hardware reciprocal estimate refined once
 // (relative error about 2^-48) instead of a correctly rounded division.
 // last2 receives |last step|^2.
-#ifndef PR_POLISH_GROUP
-#define PR_POLISH_GROUP 2
-#endif
+constexpr int kPolishGroup = 2;  // 1, 3 and 6 measured no faster
 template <int DM, int K0, int G>
 __device__ __forceinline__ void polish_group(cx<double> (&r)[DM], const cx<double> (&a)[DM + 1],
                                              int steps, double (&last2)[DM])
@@ -423,7 +420,7 @@ __device__ __forceinline__ void polish_all(cx<double> (&r)[DM], const cx<double>
                                            int steps, double (&last2)[DM], int d)
 {
     if constexpr (K0 < DM) {
-        constexpr int G = (DM - K0) < PR_POLISH_GROUP ? (DM - K0) : PR_POLISH_GROUP;
+        constexpr int G = (DM - K0) < kPolishGroup ? (DM - K0) : kPolishGroup;
         if (__ballot(K0 < d))
             polish_group<DM, K0, G>(r, a, steps, last2);
         polish_all<DM, K0 + G>(r, a, steps, last2, d);
@@ -613,25 +610,13 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
     }
 }
 
-#ifndef PR_FP64_WAVES
-#define PR_FP64_WAVES 1
-#endif
-#ifndef PR_FP32_WAVES
-#define PR_FP32_WAVES 1
-#endif
-#ifndef PR_FP64_BIN_WAVES
-#define PR_FP64_BIN_WAVES 1
-#endif
-template <bool FP32, int BIN = kBinNone>
-struct WavesPerEU {
-    static constexpr int v = FP32 ? PR_FP32_WAVES : (BIN == kBinKeep ? PR_FP64_BIN_WAVES : PR_FP64_WAVES);
-};
-
+// No occupancy hints: the register allocation as it comes (FP32 90 VGPRs, 5
+// waves per SIMD; FP64 156, 3 waves) measured faster than any forced
+// occupancy, which spills.
 // One lane per polynomial in index order (all polynomials of one degree, or
 // no degree array).
 template <bool FP32, int DM, int BIN>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32, BIN>::v)))
-void solve_flat_kernel(PolyIO io)
+__global__ __launch_bounds__(kBlock) void solve_flat_kernel(PolyIO io)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     solve_poly<FP32, DM, BIN>(io, i, i < io.n);
@@ -651,8 +636,7 @@ constexpr int kTileMax = 4096;
 constexpr int kWave = 64;
 
 template <bool FP32, int DM, int BIN, bool SELECT>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(WavesPerEU<FP32, BIN>::v)))
-void solve_tiled_kernel(PolyIO io, int tile)
+__global__ __launch_bounds__(kWave) void solve_tiled_kernel(PolyIO io, int tile)
 {
     // bucket of tile entry t: its degree (0 = invalid degree), or -1 when
     // the entry is not part of this launch's list
