@@ -44,6 +44,21 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
 
 
+def test_header_and_library_serve_a_plain_c_program(lib, tmp_path):
+    """tests/capi/example.c compiles as C11 with every warning an error and
+    links against libproots.so: the header is valid C and declares what the
+    library exports."""
+    import subprocess
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    out = tmp_path / "capi_example"
+    subprocess.run(["gcc", "-std=c11", "-O1", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                    "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "capi", "example.c"), "-o", str(out),
+                    "-L", os.path.join(ROOT, "paper_2507_02164_amd"), "-lproots",
+                    "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm"], check=True)
+    assert out.exists()
+
+
 def test_strerror_and_version(lib):
     import paper_2507_02164_amd as pr
     assert pr.strerror(0) == "success"
