@@ -138,6 +138,91 @@ def bench_mixed(args, torch, workloads, pr, dev):
     print(json.dumps({"workload": "mixed degrees 2..6, 64Mi polynomials", "n": n, "results": out}))
 
 
+def _median_ms(torch, fn, reps=15, warm=5):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[reps // 2]
+
+
+def bench_configs(args, torch, workloads, pr, dev):
+    """The other workload configurations (medians of warm repeats, inputs
+    resident in HBM): Gaussian 65,536 (eager and captured graph), known
+    roots 4 Mi (forward and backward), clustered 16 Mi (both forms), and
+    the FP64 fallback on known roots and clusters.  One JSON line."""
+    import numpy as np
+    from paper_2507_02164_amd.graph import PathGraph
+    out = {}
+
+    def flagged(s):
+        st = s.cpu().numpy().astype(np.uint32)
+        return float((st & (pr.ST_NOT_CONVERGED | pr.ST_POLISH_UNCONVERGED) != 0).mean())
+
+    log("gaussian 65,536, 256x256 image")
+    a = torch.from_numpy(workloads.gaussian(65536, 0)).to(dev)
+    win, shape = workloads.GAUSSIAN_WINDOW, (256, 256)
+    h = torch.zeros((256, 256), dtype=torch.int32, device=dev)
+    r = torch.empty((6, 65536), dtype=torch.complex128, device=dev)
+    s = torch.empty((65536,), dtype=torch.int32, device=dev)
+    for form in ("fp64", "fp32_polish"):
+        out[f"gaussian65536_{form}_solve_bin_ms"] = _median_ms(torch, lambda: (
+            h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r, status=s, out=h)))
+
+    def three():
+        pr.solve(a, None, "fp64", roots=r, status=s)
+        h.zero_()
+        pr.density(r, win, shape, status=s, out=h)
+    out["gaussian65536_fp64_three_launches_ms"] = _median_ms(torch, three)
+    g = PathGraph(a, None, "fp64", win, shape)
+    out["gaussian65536_fp64_graph_replay_ms"] = _median_ms(torch, g.replay)
+    del a, r, s, g
+
+    log("known roots 4 Mi")
+    coeffs = workloads.known_roots(4 * 2 ** 20, 0)[0]
+    a = torch.from_numpy(coeffs).to(dev)
+    n = a.shape[1]
+    cot = torch.from_numpy(workloads.cotangents(n, 1)).to(dev)
+    r = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    s = torch.empty((n,), dtype=torch.int32, device=dev)
+    gc = torch.empty_like(a)
+    for form in ("fp64", "fp32_polish"):
+        out[f"known4M_{form}_solve_ms"] = _median_ms(
+            torch, lambda: pr.solve(a, None, form, roots=r, status=s))
+        out[f"known4M_{form}_flagged"] = flagged(s)
+    out["known4M_fp32_polish_fallback_solve_ms"] = _median_ms(torch, lambda: pr.solve(
+        a, None, "fp32_polish", roots=r, status=s, flags=pr.FLAG_FP64_FALLBACK))
+    out["known4M_fp32_polish_fallback_flagged"] = flagged(s)
+    pr.solve(a, None, "fp64", roots=r, status=s)
+    out["known4M_backward_ms"] = _median_ms(
+        torch, lambda: pr.backward(a, r, cot, None, s, grad_coeffs=gc))
+    del a, r, s, gc, cot, coeffs
+
+    log("clustered 16 Mi, 1920x1080 image")
+    a = torch.from_numpy(workloads.clustered(16 * 2 ** 20, 0)[0]).to(dev)
+    n = a.shape[1]
+    r = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    s = torch.empty((n,), dtype=torch.int32, device=dev)
+    win, shape = workloads.CLUSTERED_WINDOW, (1920, 1080)
+    h = torch.zeros((1080, 1920), dtype=torch.int32, device=dev)
+    for form in ("fp32_polish", "fp64"):
+        out[f"clustered16M_{form}_solve_bin_ms"] = _median_ms(torch, lambda: (
+            h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r, status=s, out=h)),
+            reps=7, warm=2)
+        out[f"clustered16M_{form}_flagged"] = flagged(s)
+    out["clustered16M_fp32_polish_fallback_solve_ms"] = _median_ms(torch, lambda: pr.solve(
+        a, None, "fp32_polish", roots=r, status=s, flags=pr.FLAG_FP64_FALLBACK), reps=5, warm=1)
+    print(json.dumps({"workload": "other configurations", "results": out}))
+
+
 def bench_l2fit(args, torch, pr, dev, n=1 << 21, degree=6, nr=8, nt=16):
     """Sec. II-A front-end on its own: degree-6 least-squares fits of
     f(z) = sin z on 2^21 disks from 8 x 16 polar samples each.  HBM-bound:
@@ -178,9 +263,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--grid", type=int, default=4096, help="grid side; n = grid^2")
-    ap.add_argument("--workload", choices=["parametric", "mixed"], default="parametric",
+    ap.add_argument("--workload", choices=["parametric", "mixed", "configs"], default="parametric",
                     help="parametric: the default timed workload; mixed: 64M polynomials of "
-                         "degrees 2..6 (solve only, both launch layouts)")
+                         "degrees 2..6 (solve only, both launch layouts); configs: the other "
+                         "workload configurations and the FP64 fallback")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", choices=["fp32_polish", "fp64"], default=None,
                     help="run only the timed steps of one form (for profilers)")
@@ -209,6 +295,8 @@ def main():
         del src, dst
     if args.workload == "mixed":
         return bench_mixed(args, torch, workloads, pr, dev)
+    if args.workload == "configs":
+        return bench_configs(args, torch, workloads, pr, dev)
     g = args.grid
     n = g * g
     log(f"generating parametric grid {g}x{g} ({n} polynomials)")
