@@ -129,6 +129,11 @@ typedef struct pr_solve_opts {
  *            polynomial's degree.  Must not alias coeffs.
  *   status   [n] uint32 out: pr_status_bits.
  *   opts     NULL = defaults (FP64).
+ * Range: a polynomial whose root-modulus bound lies outside [2^-3, 2^10]
+ * (FP32 form) or [2^-24, 2^24] (FP64 form) is solved in
+ * the variable w = z / 2^s (an exact power-of-two change of variable, s
+ * from that bound) and its roots are returned as 2^s w; every other
+ * polynomial is solved as given.
  * Errors: PR_ERR_INVALID_ARG for a NULL coeffs/roots/status, n < 0, dmax
  * outside 1..6 or an option out of range; PR_ERR_HIP if a launch fails.
  */

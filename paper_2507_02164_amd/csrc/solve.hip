@@ -315,13 +315,15 @@ __device__ __forceinline__ void iterate(cx<T> (&h)[DM][DM], int d, int cap, bool
 }
 
 // Companion matrix, first-row form: h[0][j] = -b_{d-1-j} for j < d, ones on
-// the subdiagonal of the leading d x d block.  Built from value selects on
-// the run-time degree, so every matrix entry is written at a fixed
-// location (a store whose address depended on d would force the matrix out
-// of registers).
+// the subdiagonal of the leading d x d block -- of the scaled polynomial
+// q(w) = p(2^s w) / 2^(s d), i.e. h[0][j] = -b_{d-1-j} 2^(-s (j+1)) (exact:
+// a power-of-two scale), whose roots are w = z / 2^s.  Built from value
+// selects on the run-time degree, so every matrix entry is written at a
+// fixed location (a store whose address depended on d would force the
+// matrix out of registers).
 template <typename T, int DM>
 __device__ __forceinline__ void companion(cx<T> (&h)[DM][DM], int d,
-                                          const cx<double> (&b)[DM + 1])
+                                          const cx<double> (&b)[DM + 1], int s)
 {
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
@@ -330,11 +332,52 @@ __device__ __forceinline__ void companion(cx<T> (&h)[DM][DM], int d,
         for (int D = j + 1; D <= DM; ++D)
             if (d == D)
                 v = b[D - 1 - j];
-        h[0][j] = {(T)(-v.re), (T)(-v.im)};
+        const int e = -s * (j + 1);
+        h[0][j] = {(T)(-__builtin_ldexp(v.re, e)), (T)(-__builtin_ldexp(v.im, e))};
     }
 #pragma unroll
     for (int i = 1; i < DM; ++i)
         h[i][i - 1] = {i < d ? T(1) : T(0), T(0)};
+}
+
+// Range of the sweeps.  The Givens pair squares matrix entries, so FP32
+// sweeps overflow for entries beyond about 2^63 and lose tiny ones below
+// about 2^-63 (FP64: 2^511), and a companion matrix whose first row spans
+// many binades loses relative accuracy on its small roots.  A polynomial
+// whose root bound lies outside [2^lo, 2^hi] of FreeRange (FP32: 2^-3 ..
+// 2^10, FP64: 2^-24 .. 2^24) is therefore solved as q(w) = p(2^s w) / 2^(s d), with s
+// the exponent of a bound on its root moduli (Fujiwara: |z| <= 2 max_k
+// |b_{d-k}|^(1/k)), so that the sweeps see roots of modulus about 1; the
+// roots come back as z = 2^s w, exactly.  Ordinary polynomials get s = 0 and
+// the very same arithmetic as without scaling.  s need not be exact (any
+// power of two scales exactly), so the k-th roots use the hardware
+// reciprocal estimate.
+template <typename T>
+struct FreeRange;
+template <>
+struct FreeRange<float> {  // below 2^-3 FP32 sweeps lose the small roots' digits
+    static constexpr int lo = -3, hi = 10;
+};
+template <>
+struct FreeRange<double> {
+    static constexpr int lo = -24, hi = 24;
+};
+
+template <typename T, int DM>
+__device__ __forceinline__ int root_scale(const cx<double> (&b)[DM + 1], int d)
+{
+    float bound = -1e30f;  // log2 of the root bound, up to rounding
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        const double m = cabs1_d(b[j]);
+        if (j < d && m > 0.0) {
+            const float k = (float)(d - j);  // b_j = b_{d-k}
+            const float e = (float)(__builtin_amdgcn_frexp_exp(m) + 1);  // >= log2(2m)
+            bound = fmaxf(bound, e * __builtin_amdgcn_rcpf(k));
+        }
+    }
+    const int s = bound > -1e29f ? (int)ceilf(bound) : 0;
+    return (s > FreeRange<T>::hi || s < FreeRange<T>::lo) ? s : 0;
 }
 
 // Load a_0..a_d (zeros above d), validate, and normalise to b = a / a_d.
@@ -368,7 +411,8 @@ __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs
 
 // Newton polish in FP64 on the original coefficients a (zeros above the
 // degree, so Horner from DM gives the same value as from the degree):
-// r <- r - p(r) / p'(r), a step skipped where p'(r) is zero or not finite.
+// r <- r - p(r) / p'(r), a step skipped where |p'(r)|^2 is zero, subnormal
+// or not finite (and then counted as unconverged unless p(r) == 0).
 // The roots K0..K0+G-1 are polished together: their Horner recurrences are
 // independent, and interleaving them hides the FP64 multiply-add latency
 // that a single chain would wait on.  The step needs 1/|p'|^2 only to the
@@ -401,14 +445,18 @@ __device__ __forceinline__ void polish_group(cx<double> (&r)[DM], const cx<doubl
         for (int g = 0; g < G; ++g) {
             const double den = norm2(dp[g]);
             cx<double> delta = {0.0, 0.0};
-            if (den >= 0x1p-1022 && isfinite(den)) {
+            const bool step = den >= 0x1p-1022 && isfinite(den);
+            if (step) {
                 const cx<double> q = p[g] * conj(dp[g]);
                 const double y0 = __builtin_amdgcn_rcp(den);
                 const double inv = __builtin_fma(y0, __builtin_fma(-den, y0, 1.0), y0);
                 delta = {q.re * inv, q.im * inv};
             }
             r[K0 + g] = r[K0 + g] - delta;
-            last2[K0 + g] = norm2(delta);
+            // a step that cannot be taken counts as converged only at an
+            // exact root
+            const bool at_root = p[g].re == 0.0 && p[g].im == 0.0;
+            last2[K0 + g] = step ? norm2(delta) : (at_root ? 0.0 : __builtin_inf());
         }
     }
 }
@@ -502,12 +550,14 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
 #pragma unroll
         for (int c = (r > 0 ? r - 1 : 0); c < DM; ++c)
             h[r][c] = {T(0), T(0)};
-    companion<T, DM>(h, dd, b);
+    const int sc = ok ? root_scale<T, DM>(b, d) : 0;  // roots come back as 2^sc w
+    companion<T, DM>(h, dd, b, sc);
     const bool fixed = (io.flags & PR_FLAG_FIXED_STEPS) != 0;
     const bool exc = !(io.flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT) && !fixed;
 
     if constexpr (!FP32) {
-        iterate<double, DM>(h, dd, io.cap, exc, fixed, st, io.iters, n, i, [&](int k, cx<double> v) {
+        iterate<double, DM>(h, dd, io.cap, exc, fixed, st, io.iters, n, i, [&](int k, cx<double> w) {
+            const cx<double> v = {__builtin_ldexp(w.re, sc), __builtin_ldexp(w.im, sc)};
             if (store)
                 io.roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
             if constexpr (BIN == kBinKeep) {
@@ -520,12 +570,13 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
             }
         });
         if (ok) {
+            const cx<double> v0 = {__builtin_ldexp(h[0][0].re, sc), __builtin_ldexp(h[0][0].im, sc)};
             if (store)
-                io.roots[i] = make_double2(h[0][0].re, h[0][0].im);
+                io.roots[i] = make_double2(v0.re, v0.im);
             if constexpr (BIN == kBinKeep)
-                bins[0] = pixel_of(h[0][0].re, h[0][0].im, io.win);
+                bins[0] = pixel_of(v0.re, v0.im, io.win);
             if constexpr (BIN == kBinReread) {
-                bins[0] = pixel_of(h[0][0].re, h[0][0].im, io.win);
+                bins[0] = pixel_of(v0.re, v0.im, io.win);
 #pragma unroll
                 for (int k = 1; k < DM; ++k)
                     if (k < dd) {
@@ -555,8 +606,11 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
             for (int k = 0; k <= DM; ++k) {
                 a[k] = {0.0, 0.0};
                 if (k <= d) {
+                    // a_k 2^(s (k - d)): the coefficients of 2^(-s d) p(2^s w),
+                    // so that the polish below runs in the sweeps' variable w
                     const double2 v = io.coeffs_again[(int64_t)k * n + i];
-                    a[k] = {v.x, v.y};
+                    const int e = sc * (k - d);
+                    a[k] = {__builtin_ldexp(v.x, e), __builtin_ldexp(v.y, e)};
                 }
             }
             cx<double> r[DM];
@@ -589,6 +643,9 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
                     }
             if (bad)
                 st |= PR_ST_POLISH_UNCONVERGED;
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                r[k] = {__builtin_ldexp(r[k].re, sc), __builtin_ldexp(r[k].im, sc)};  // z = 2^s w
 #pragma unroll
             for (int k = 0; k < DM; ++k)
                 if (k < d) {
