@@ -667,8 +667,8 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
     }
 }
 
-// No occupancy hints: the register allocation as it comes (FP32 90 VGPRs, 5
-// waves per SIMD; FP64 156, 3 waves) measured faster than any forced
+// No occupancy hints: the register allocation as it comes (FP32 96 VGPRs, 5
+// waves per SIMD; FP64 158, 3 waves) measured faster than any forced
 // occupancy, which spills.
 // One lane per polynomial in index order (all polynomials of one degree, or
 // no degree array).
