@@ -40,31 +40,19 @@ PEAK_HBM = 8.0e12            # B/s
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "solve_bin_fp32_polish_parametric4096_traffic.json")
 
 
-def code_digest(paths):
-    """SHA-256 of the given source files with comments and whitespace
-    removed: an edit to a comment leaves the kernel, and the digest, as it
-    was."""
-    import hashlib
-    import re
-    h = hashlib.sha256()
-    for src in paths:
-        with open(os.path.join(ROOT, src)) as f:
-            text = f.read()
-        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-        text = re.sub(r"//[^\n]*", " ", text)
-        h.update(" ".join(text.split()).encode())
-    return h.hexdigest()
-
-
 def measured_traffic(form, grid):
     """HBM bytes per launch of the solve + bin kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE record (calibrated against a copy kernel), or
     None when that record does not describe the kernel as it is now (its
-    sources changed since the counters were taken) or this workload."""
+    gfx950 instructions, recorded by the build, differ from the profiled
+    ones) or this workload."""
     if form != "fp32_polish" or grid != 4096 or not os.path.exists(TRAFFIC_RECORD):
         return None
+    digests = os.path.join(ROOT, "paper_2507_02164_amd", "kernel_isa.json")
+    if not os.path.exists(digests):
+        return None
     rec = json.load(open(TRAFFIC_RECORD))
-    if code_digest(rec["sources"]) != rec.get("sources_code_sha256"):
+    if json.load(open(digests)).get(rec["kernel_symbol"]) != rec["kernel_isa_sha256"]:
         return None
     return rec["hbm_bytes_per_launch"]
 

@@ -94,7 +94,7 @@ static int solve_common(const pr_complex* coeffs, const int32_t* degrees, int64_
         return PR_ERR_INVALID_ARG;
     if (n == 0)
         return PR_OK;
-    if (n > (int64_t)0x7fffffff * 256)
+    if (n > kMaxSolveBatch)
         return PR_ERR_INVALID_ARG;
     SolveArgs a;
     a.coeffs = coeffs;
@@ -158,7 +158,7 @@ static int density_common(const pr_complex* roots, const int32_t* degrees,
         return rc;
     if (n == 0)
         return PR_OK;
-    if (n > (int64_t)0x7fffffff * 256)
+    if (n > kMaxStreamBatch)
         return PR_ERR_INVALID_ARG;
     DensityArgs a;
     a.roots = roots;
@@ -223,7 +223,7 @@ extern "C" int pr_l2fit(const pr_complex* samples, int64_t n, int32_t degree, in
         return PR_ERR_INVALID_ARG;
     if (n == 0)
         return PR_OK;
-    if (n > (int64_t)0x7fffffff * 256)
+    if (n > kMaxStreamBatch)
         return PR_ERR_INVALID_ARG;
     L2FitArgs a;
     a.samples = samples;
@@ -245,7 +245,7 @@ extern "C" int pr_backward(const pr_complex* coeffs, const int32_t* degrees,
         return PR_ERR_INVALID_ARG;
     if (n == 0)
         return PR_OK;
-    if (n > (int64_t)0x7fffffff * 256)
+    if (n > kMaxStreamBatch)
         return PR_ERR_INVALID_ARG;
     BackwardArgs a;
     a.coeffs = coeffs;

@@ -10,6 +10,11 @@
 
 namespace proots {
 
+// Largest batch a launch covers: a one-dimensional grid holds at most
+// 2^31 - 1 blocks (64-lane blocks for the solve kernels, 256 for the others).
+constexpr int64_t kMaxSolveBatch = (int64_t)0x7fffffff * 64;
+constexpr int64_t kMaxStreamBatch = (int64_t)0x7fffffff * 256 - 8 * 256;
+
 struct SolveArgs {
     const pr_complex* coeffs;
     const int32_t* degrees;

@@ -59,6 +59,21 @@ def test_header_and_library_serve_a_plain_c_program(lib, tmp_path):
     assert out.exists()
 
 
+def test_build_records_kernel_instruction_digests(lib):
+    """The build writes a digest of every solve kernel's instructions; the
+    parser keeps instruction lines only (labels, directives and comments do
+    not change a digest)."""
+    import json
+    from paper_2507_02164_amd import build as b
+    d = json.load(open(b.ISA_DIGESTS))
+    timed = "_ZN6proots12_GLOBAL__N_117solve_flat_kernelILb1ELi6ELi2EEEvNS0_6PolyIOE"
+    assert timed in d and len(d[timed]) == 64
+    asm = "_Zk:\n  v_add_f32 v0, v1, v2 ; c\n.LBB0_1:\n  .p2align 2\n  s_endpgm\n"
+    asm2 = "_Zk: ; other comment\n  v_add_f32 v0, v1, v2\n.LBB9_9:\n  s_endpgm ; end\n"
+    assert b.isa_digests(asm) == b.isa_digests(asm2)
+    assert b.isa_digests(asm) != b.isa_digests(asm.replace("v2", "v3"))
+
+
 def test_strerror_and_version(lib):
     import paper_2507_02164_amd as pr
     assert pr.strerror(0) == "success"
@@ -92,6 +107,8 @@ def test_solve_argument_validation(lib):
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
     fb = pr.SolveOpts(precision=pr.FP32_POLISH, flags=pr.FLAG_FP64_FALLBACK | pr.FLAG_FIXED_STEPS)
     assert lib.pr_solve(fake, None, 0, 6, fake, fake, ctypes.byref(fb), None) == pr.PR_OK
+    # more polynomials than one launch's grid can cover
+    assert lib.pr_solve(fake, None, 0x7fffffff * 64 + 1, 6, fake, fake, None, None) == pr.PR_ERR_INVALID_ARG
     # n == 0 is a valid no-op: nothing is enqueued, the arrays may be NULL
     assert lib.pr_solve(fake, None, 0, 6, fake, fake, ctypes.byref(opts), None) == pr.PR_OK
     assert lib.pr_solve(None, None, 0, 6, None, None, None, None) == pr.PR_OK
