@@ -198,11 +198,18 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
         // (numerically) zero -- NaN fails the test too; otherwise
         // (c, s) = (1, 0) and both entries stay
         const bool go = act && rotates(n2);
-        const cx<T> c = {pick(go, a.re * inv, T(1)), pick(go, -a.im * inv, T(0))};
-        const cx<T> s = {pick(go, b.re * inv, T(0)), pick(go, -b.im * inv, T(0))};
-        // the rotation maps (h[r-1][r-1], h[r][r-1]) to (rho, 0)
-        h[r - 1][r - 1] = {pick(go, n2 * inv, a.re), pick(go, T(0), a.im)};
-        h[r][r - 1] = {pick(go, T(0), b.re), pick(go, T(0), b.im)};
+        // masking by arithmetic, two selects in all: a rotating lane takes
+        // 1/rho and 0, a lane that keeps its entries 0 and 1, so that
+        // c = conj(a)/rho or 1, s = conj(b)/rho or 0, and the rotation maps
+        // (h[r-1][r-1], h[r][r-1]) to (rho, 0) or leaves them (their values;
+        // an entry whose square overflowed would turn NaN, as its rotation
+        // would anyway)
+        const T ig = pick(go, inv, T(0));
+        const T keep = pick(go, T(0), T(1));
+        const cx<T> c = {a.re * ig + keep, -a.im * ig};
+        const cx<T> s = {b.re * ig, -b.im * ig};
+        h[r - 1][r - 1] = {n2 * ig + keep * a.re, keep * a.im};
+        h[r][r - 1] = {keep * b.re, keep * b.im};
 #pragma unroll
         for (int j = r; j < M; ++j)
             rot_rows(h[r - 1][j], h[r][j], c, s);
