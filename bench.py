@@ -275,8 +275,9 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   f"--gpus {args.gpus} is not supported (polynomials shard "
-                                   "trivially; see DESIGN.md)"}))
+                                   f"--gpus {args.gpus} is not supported.  Polynomials are "
+                                   "independent: N GPUs would each solve a contiguous 1/N of "
+                                   "the batch and sum their int32 images with one all-reduce."}))
         sys.exit(2)
 
     import torch
