@@ -13,7 +13,10 @@ What each function follows in arXiv 2507.02164:
                and Sec. II-C (Givens equation, two-row then two-column
                in-place update, the loop shape of Alg. 2), with a
                convergence test and exceptional shift where the paper has a
-               fixed iteration count (``fixed_t`` reproduces Alg. 2).
+               fixed iteration count (``fixed_t`` reproduces Alg. 2), and,
+               with ``FLAG_WILKINSON_SHIFT``, Wilkinson's shift (the
+               eigenvalue of the trailing 2 x 2 block nearest its bottom
+               entry) in place of Alg. 1's bottom-right entry.
   density   -- Sec. III, roots converted to pixel coordinates and counted.
   backward  -- not in the paper: the implicit-function derivative
                dr/da_k = -r^k / p'(r) of a simple root.
@@ -37,6 +40,7 @@ ST_NOT_CONVERGED = 0x8
 ST_SINGULAR_DERIV = 0x20
 
 FLAG_NO_EXCEPTIONAL_SHIFT = 0x1
+FLAG_WILKINSON_SHIFT = 0x8
 
 _lib = None
 
@@ -76,6 +80,8 @@ def _load():
         lib.oracle_givens.restype = None
         lib.oracle_qr_step.argtypes = [ctypes.c_int, P, P]
         lib.oracle_qr_step.restype = None
+        lib.oracle_wilkinson_shift.argtypes = [P, P, P, P, P]
+        lib.oracle_wilkinson_shift.restype = None
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -218,6 +224,15 @@ def givens(a: complex, b: complex):
     C = np.zeros(2); S = np.zeros(2)
     _load().oracle_givens(_ptr(A), _ptr(B), _ptr(C), _ptr(S))
     return complex(C[0], C[1]), complex(S[0], S[1])
+
+
+def wilkinson_shift(a: complex, b: complex, c: complex, e: complex) -> complex:
+    """Eigenvalue of [[a, b], [c, e]] nearest e (the shift taken with
+    ``FLAG_WILKINSON_SHIFT`` instead of Alg. 1's bottom-right entry)."""
+    v = [np.array([z.real, z.imag]) for z in (complex(a), complex(b), complex(c), complex(e))]
+    mu = np.zeros(2)
+    _load().oracle_wilkinson_shift(*(_ptr(x) for x in v), _ptr(mu))
+    return complex(mu[0], mu[1])
 
 
 def qr_step(H, shift: complex):

@@ -42,7 +42,11 @@
  *     s += cabs1(h[m-1][m-2]) * (0.75 + 0.5i); cap of 30 iterations per
  *     level, after which the level deflates anyway and NOT_CONVERGED is set;
  *   - a fixed-T mode (flag) reproduces Alg. 2 literally: exactly T QR steps
- *     per level, no test, no exceptional shift.
+ *     per level, no test, no exceptional shift;
+ *   - an optional shift (flag): instead of Alg. 1's bottom-right entry, the
+ *     eigenvalue of the trailing 2 x 2 block nearest that entry (Wilkinson's
+ *     shift, the textbook choice for single-shift QR; not in the paper).
+ *     It is still one complex shift per QR step; only its value changes.
  */
 #include <complex.h>
 #include <math.h>
@@ -65,6 +69,7 @@
 /* flags for oracle_solve */
 #define OFLAG_NO_EXCEPTIONAL_SHIFT 0x1u
 #define OFLAG_FIXED_T 0x2u
+#define OFLAG_WILKINSON_SHIFT 0x8u
 
 #define ODMAX 6
 
@@ -148,6 +153,37 @@ void oracle_qr_step(int m, double *H_ri, const double *shift_ri)
     }
 }
 
+/* Wilkinson's shift: the eigenvalue of the 2 x 2 block [[a, b], [c, e]]
+ * nearest e.  With t = (a - e) / 2 the eigenvalues are e + t + r and
+ * e + t - r, r^2 = t^2 + b c.  Of the two square roots r is the one with
+ * Re(conj(t) r) >= 0, so that |t + r| >= |t - r| and e + t - r is the nearer
+ * eigenvalue; it equals e - b c / (t + r) (multiply by (t + r) / (t + r) and
+ * use r^2 - t^2 = b c), which is the form evaluated.  t + r == 0 forces
+ * t == r == 0, hence b c == 0 and a double eigenvalue e. */
+static cplx wilkinson_shift(cplx a, cplx b, cplx c, cplx e)
+{
+    cplx t = 0.5 * (a - e);
+    cplx bc = b * c;
+    cplx r = csqrt(t * t + bc);
+    if (creal(t) * creal(r) + cimag(t) * cimag(r) < 0.0)
+        r = -r;
+    cplx den = t + r;
+    if (den == 0.0)
+        return e;
+    return e - bc / den;
+}
+
+/* Exposed for tests: Wilkinson's shift of [[a, b], [c, e]], each complex
+ * value as interleaved (re, im) doubles. */
+void oracle_wilkinson_shift(const double *a_ri, const double *b_ri, const double *c_ri,
+                            const double *e_ri, double *mu_ri)
+{
+    cplx mu = wilkinson_shift(a_ri[0] + I * a_ri[1], b_ri[0] + I * b_ri[1],
+                              c_ri[0] + I * c_ri[1], e_ri[0] + I * e_ri[1]);
+    mu_ri[0] = creal(mu);
+    mu_ri[1] = cimag(mu);
+}
+
 /* Roots of one polynomial of degree d with coefficients a[0..d] (a[d]
  * leading).  eig[0..d-1] receives the eigenvalues in deflation order
  * (eig[d-1] is found first, eig[0] last, as in Alg. 1).  its[m-2] receives
@@ -207,8 +243,12 @@ static unsigned solve_one(int d, const cplx *a, cplx *eig, int *its_out,
                     break;
                 }
             }
-            /* Alg. 1: the shift is the current bottom-right entry. */
+            /* Alg. 1: the shift is the current bottom-right entry, or, with
+             * the flag, Wilkinson's shift of the trailing 2 x 2 block. */
             cplx s = H[(m - 1) * d + (m - 1)];
+            if (flags & OFLAG_WILKINSON_SHIFT)
+                s = wilkinson_shift(H[(m - 2) * d + (m - 2)], H[(m - 2) * d + (m - 1)], hsub,
+                                    H[(m - 1) * d + (m - 1)]);
             if (fixed_t <= 0 && !(flags & OFLAG_NO_EXCEPTIONAL_SHIFT) && (its == 10 || its == 20))
                 s += cabs1(hsub) * (0.75 + 0.5 * I);
             qr_step(m, d, H, s);

@@ -50,7 +50,8 @@ def _poly_from_roots_exact(roots):
     return c
 
 
-def test_known_roots_lattice():
+@pytest.mark.parametrize("flags", [0, oracle.FLAG_WILKINSON_SHIFT])
+def test_known_roots_lattice(flags):
     """Roots on the lattice (p + q i)/4, |p|, |q| <= 8, distinct: the
     expanded coefficients are exact in FP64, so the true roots are known.
     Error bound: first-order perturbation |dr| <= C u ||b||^2 sum|r|^k / |p'(r)|
@@ -72,7 +73,7 @@ def test_known_roots_lattice():
                 assert Fraction(fr) == cr and Fraction(fi) == ci      # exact in FP64
                 coeffs[k, i] = complex(fr, fi)
             truth[:, i] = [complex(float(p), float(q)) for (p, q) in rts]
-        roots, st = oracle.solve(coeffs)
+        roots, st = oracle.solve(coeffs, flags=flags)
         assert np.all(st == 0)
         m = match(roots, truth)
         bnorm = np.abs(coeffs[:d]).max(axis=0)
