@@ -47,6 +47,7 @@
  *     eigenvalue of the trailing 2 x 2 block nearest that entry (Wilkinson's
  *     shift, the textbook choice for single-shift QR; not in the paper).
  *     It is still one complex shift per QR step; only its value changes.
+ *     The fixed-T mode, being Alg. 2 literally, keeps Alg. 1's shift.
  */
 #include <complex.h>
 #include <math.h>
@@ -246,7 +247,7 @@ static unsigned solve_one(int d, const cplx *a, cplx *eig, int *its_out,
             /* Alg. 1: the shift is the current bottom-right entry, or, with
              * the flag, Wilkinson's shift of the trailing 2 x 2 block. */
             cplx s = H[(m - 1) * d + (m - 1)];
-            if (flags & OFLAG_WILKINSON_SHIFT)
+            if ((flags & OFLAG_WILKINSON_SHIFT) && fixed_t <= 0)
                 s = wilkinson_shift(H[(m - 2) * d + (m - 2)], H[(m - 2) * d + (m - 1)], hsub,
                                     H[(m - 1) * d + (m - 1)]);
             if (fixed_t <= 0 && !(flags & OFLAG_NO_EXCEPTIONAL_SHIFT) && (its == 10 || its == 20))
