@@ -30,8 +30,12 @@ if ROOT not in sys.path:
 
 # Per-QR-step FLOPs at level m (band-trimmed complex Givens sweep: 28 per
 # two-entry rotation pair over m(m+1)-2 pairs, 11 per Givens pair, 4m for
-# the shift), and polish FLOPs per root per Newton step at degree d.
+# subtracting and adding back the shift), the FLOPs of computing the default
+# (Wilkinson) shift per step -- D = a - e 2, bc 6, 4bc 2, D^2 5, q 2,
+# |q| 4, w and v 6, side test 3, e + (D - R)/2 6 -- and polish FLOPs per
+# root per Newton step at degree d.
 F_LEVEL = {2: 131, 3: 314, 4: 553, 5: 848, 6: 1199}
+F_WILKINSON = 36
 PEAK_FP64 = 78.6e12          # MI355X vector FP64, FLOP/s
 PEAK_FP32 = 157.3e12         # MI355X vector FP32 (published)
 PEAK_HBM = 8.0e12            # B/s
@@ -66,7 +70,7 @@ def log(msg):
     sys.stderr.flush()
 
 
-def lockstep_flops(iters, wave=64):
+def lockstep_flops(iters, wave=64, shift=F_WILKINSON):
     """FLOPs the level-synchronous waves execute: per wave of 64 consecutive
     polynomials and per level, the largest step count times F(m) times 64."""
     it = iters.astype(np.float64)
@@ -75,14 +79,16 @@ def lockstep_flops(iters, wave=64):
     tot = 0.0
     for m in range(2, 7):
         w = it[m - 2, :nw * wave].reshape(nw, wave).max(axis=1)
-        tot += w.sum() * F_LEVEL[m] * wave
+        tot += w.sum() * (F_LEVEL[m] + shift) * wave
     return tot
 
 
-def algorithmic_flops(iters):
-    """Sum over polynomials and levels of steps x F(m).  iters [5, n] int."""
+def algorithmic_flops(iters, shift=F_WILKINSON):
+    """Sum over polynomials and levels of steps x (F(m) + the shift's own
+    FLOPs: F_WILKINSON for the default shift, 0 for Alg. 1's bottom entry).
+    iters [5, n] int."""
     it = iters.astype(np.float64)
-    return float(sum(it[m - 2].sum() * F_LEVEL[m] for m in range(2, 7)))
+    return float(sum(it[m - 2].sum() * (F_LEVEL[m] + shift) for m in range(2, 7)))
 
 
 def cpu_baseline(coeffs_host, target_s=10.0):
@@ -90,19 +96,21 @@ def cpu_baseline(coeffs_host, target_s=10.0):
     threads = oracle.max_threads()
     n_total = coeffs_host.shape[1]
     probe = min(65536, n_total)
+    # the same method as the GPU path: Wilkinson's shift
+    flags = oracle.FLAG_WILKINSON_SHIFT
     t0 = time.perf_counter()
-    oracle.solve(coeffs_host[:, :probe])
+    oracle.solve(coeffs_host[:, :probe], flags=flags)
     dt = time.perf_counter() - t0
     rate = probe / max(dt, 1e-9)
     n = int(min(n_total, max(probe, rate * target_s)))
     sample = np.ascontiguousarray(coeffs_host[:, :n])
     t0 = time.perf_counter()
-    roots, st = oracle.solve(sample)
+    roots, st = oracle.solve(sample, flags=flags)
     dt = time.perf_counter() - t0
     return {
         "value": n / dt, "unit": "polys/s", "cores": threads, "kind": "oracle",
         "sample": f"first {n} polynomials of the same grid (rows 0..{(n - 1) // 4096} of 4096), "
-                  f"FP64 oracle solve only, {dt:.1f} s",
+                  f"FP64 oracle solve only, Wilkinson shift as on the GPU, {dt:.1f} s",
         "host_cpu": platform.processor() or platform.machine(),
     }, roots, n
 
@@ -396,6 +404,39 @@ def main():
             solve_alg_tflops=flops / (solve_ms * 1e-3) / 1e12)
         log(f"{form}: separate launches: step {sep_ms:.3f} ms, solve {solve_ms:.3f} ms, "
             f"density {dens_ms:.3f} ms")
+
+        # context: the same fused launch with Alg. 1's shift (the bottom-right
+        # entry) in place of the default Wilkinson shift
+        _, _, its_r = pr.solve(a, None, form, iter_counts=True, roots=roots, status=status,
+                               flags=pr.FLAG_RAYLEIGH_SHIFT)
+        torch.cuda.synchronize()
+        its_r = its_r.cpu().numpy()
+
+        def bin_rayleigh():
+            hist.zero_()
+            pr.solve_bin(a, win, shape, None, form, roots=roots, status=status, out=hist,
+                         flags=pr.FLAG_RAYLEIGH_SHIFT)
+
+        for _ in range(args.warmup):
+            bin_rayleigh()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            bin_rayleigh()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ray_ms = e0.elapsed_time(e1) / args.steps
+        fl_r = algorithmic_flops(its_r, shift=0) + (n * polish_flops(6, 2)
+                                                    if form == "fp32_polish" else 0)
+        res[form]["paper_shift"] = dict(
+            zero_and_solve_bin_ms=ray_ms, mean_qr_steps=float(its_r.sum(axis=0).mean()),
+            alg_tflops=fl_r / (ray_ms * 1e-3) / 1e12,
+            note="PR_FLAG_RAYLEIGH_SHIFT: Alg. 1's bottom-entry shift; image clear + "
+                 "solve_bin per step, no backward")
+        log(f"{form}: with Alg. 1's shift: clear + solve+bin {ray_ms:.3f} ms, "
+            f"{its_r.sum(axis=0).mean():.2f} steps per polynomial")
 
     main_form = forms[0]
     r = res[main_form]

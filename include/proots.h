@@ -81,19 +81,27 @@ typedef enum pr_precision {
 
 /* Option flags. */
 enum pr_solve_flags {
-    PR_FLAG_NO_EXCEPTIONAL_SHIFT = 1u << 0, /* debug: pure Rayleigh shift only (a polynomial
-                                               such as z^d - c then stalls to the cap) */
+    PR_FLAG_NO_EXCEPTIONAL_SHIFT = 1u << 0, /* debug: no exceptional shift (a polynomial such
+                                               as z^d - c, d >= 3, then stalls to the cap) */
     PR_FLAG_FIXED_STEPS = 1u << 1,          /* Alg. 2 literally: every level takes exactly
-                                               max_iter_per_level QR steps with the pure
-                                               Rayleigh shift, no convergence test and no
+                                               max_iter_per_level QR steps shifted by Alg. 1's
+                                               bottom-right entry, no convergence test and no
                                                exceptional shift; NOT_CONVERGED is never set */
-    PR_FLAG_FP64_FALLBACK = 1u << 2         /* FP32 form: every polynomial whose FP32 result
+    PR_FLAG_FP64_FALLBACK = 1u << 2,        /* FP32 form: every polynomial whose FP32 result
                                                ends NOT_CONVERGED or POLISH_UNCONVERGED is
                                                solved again by the FP64 form (a second launch
                                                on the same stream that reads the status array
                                                and solves only those); its roots, status (with
                                                PR_ST_RESOLVED_FP64) and iteration counts are
                                                then the FP64 solve's.  No effect on PR_FP64 */
+    PR_FLAG_RAYLEIGH_SHIFT = 1u << 3        /* shift each QR step by Alg. 1's choice, the
+                                               bottom-right entry itself.  Default: the
+                                               eigenvalue of the trailing 2 x 2 block nearest
+                                               that entry (Wilkinson's shift), one complex
+                                               shift per step as well, with fewer steps per
+                                               level (a 2 x 2 block deflates in one); where
+                                               its value is not finite (FP32 entries beyond
+                                               about 2^31) a step takes the bottom entry */
 };
 
 /* Options of pr_solve.  Zero-initialised = defaults. */

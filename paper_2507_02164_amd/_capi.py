@@ -34,6 +34,7 @@ PRECISIONS = {"fp64": FP64, "fp32_polish": FP32_POLISH}
 FLAG_NO_EXCEPTIONAL_SHIFT = 1 << 0
 FLAG_FIXED_STEPS = 1 << 1
 FLAG_FP64_FALLBACK = 1 << 2
+FLAG_RAYLEIGH_SHIFT = 1 << 3
 
 
 class ProotsError(RuntimeError):

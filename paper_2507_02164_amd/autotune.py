@@ -7,7 +7,11 @@ the GPU (HIP events, median of repeats) and keeps the fastest:
   * grid_blocks  -- one-wave blocks of the persistent launch, per compute unit,
   * cap          -- QR steps per level before NOT_CONVERGED; a cap is only
                     eligible if it flags no polynomial of the sample that the
-                    default cap of 30 does not flag.
+                    default cap of 30 does not flag, and a smaller cap is only
+                    taken if it is faster than the default's best layout by
+                    more than CAP_MARGIN (a cap that no lane reaches changes
+                    nothing but the result on harder inputs, and timing noise
+                    alone would otherwise pick it half of the time).
 
 Results go to a JSON cache keyed by architecture, form, dmax and degree mix
 (``PROOTS_TUNE_CACHE`` overrides the path).  ``tuned_options`` reads it;
@@ -32,6 +36,8 @@ DEFAULT_CACHE = os.path.join(_HERE, "tuning", "tune_cache.json")
 TILES = (512, 1024, 2048, 4096)
 BLOCKS_PER_CU = (8, 16, 32, 64, 128)
 CAPS = (20, 24, 30)
+DEFAULT_CAP = 30
+CAP_MARGIN = 0.03
 
 _cache = None
 
@@ -122,6 +128,11 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
             trials.append({"options": o, "ms": ms})
             log(f"  {precision} {o}: {ms:.3f} ms")
     best = min(trials, key=lambda t: t["ms"])
+    at_default = [t for t in trials if t["options"]["max_iter_per_level"] == DEFAULT_CAP]
+    if at_default:
+        best_default = min(at_default, key=lambda t: t["ms"])
+        if best_default["ms"] <= best["ms"] * (1 + CAP_MARGIN):
+            best = best_default
     return {"options": best["options"], "ms": best["ms"], "n": n, "trials": trials,
             "eligible_caps": caps, "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
 

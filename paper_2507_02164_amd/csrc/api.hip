@@ -88,7 +88,8 @@ static int solve_common(const pr_complex* coeffs, const int32_t* degrees, int64_
     if (!(o.polish_tol >= 0.0 && o.polish_tol < 1.0))
         return PR_ERR_INVALID_ARG;
     if (o.flags &
-        ~(uint32_t)(PR_FLAG_NO_EXCEPTIONAL_SHIFT | PR_FLAG_FIXED_STEPS | PR_FLAG_FP64_FALLBACK))
+        ~(uint32_t)(PR_FLAG_NO_EXCEPTIONAL_SHIFT | PR_FLAG_FIXED_STEPS | PR_FLAG_FP64_FALLBACK |
+                    PR_FLAG_RAYLEIGH_SHIFT))
         return PR_ERR_UNSUPPORTED;
     if (o.tile < -1 || o.tile > max_tile() || o.grid_blocks < 0)
         return PR_ERR_INVALID_ARG;

@@ -103,9 +103,10 @@ def test_solve_argument_validation(lib):
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_INVALID_ARG
     bad = pr.SolveOpts(flags=0x80)
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
-    bad = pr.SolveOpts(flags=0x8)
+    bad = pr.SolveOpts(flags=0x10)
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
-    fb = pr.SolveOpts(precision=pr.FP32_POLISH, flags=pr.FLAG_FP64_FALLBACK | pr.FLAG_FIXED_STEPS)
+    fb = pr.SolveOpts(precision=pr.FP32_POLISH, flags=pr.FLAG_FP64_FALLBACK | pr.FLAG_FIXED_STEPS |
+                      pr.FLAG_RAYLEIGH_SHIFT)
     assert lib.pr_solve(fake, None, 0, 6, fake, fake, ctypes.byref(fb), None) == pr.PR_OK
     # more polynomials than one launch's grid can cover
     assert lib.pr_solve(fake, None, 0x7fffffff * 64 + 1, 6, fake, fake, None, None) == pr.PR_ERR_INVALID_ARG

@@ -20,6 +20,10 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
 pr = pytest.importorskip("paper_2507_02164_amd")
 
+# the oracle with the library's default shift (Wilkinson's); tests of Alg. 1's
+# shift pass PR_FLAG_RAYLEIGH_SHIFT to the library and no flag to the oracle
+OW = oracle.FLAG_WILKINSON_SHIFT
+
 
 def _say(msg):
     sys.stdout.write(f"  {msg}\n")
@@ -37,7 +41,7 @@ def test_parametric_full_both_forms_and_image():
     n = a.shape[1]
     ca = to_dev(a)
     _say("oracle on all 16.7M polynomials")
-    ref, ref_st = oracle.solve(a)
+    ref, ref_st = oracle.solve(a, flags=OW)
     idx = _sample(n, 8192)
     kappa = rel_condition(a[:, idx], ref[:, idx])
     for form in ("fp32_polish", "fp64"):
@@ -76,7 +80,7 @@ def test_mixed_full_fp32_polish():
     assert flagged_all.mean() < 1e-2
     # every flagged polynomial plus the sample are checked against the oracle
     chk = np.union1d(idx, np.nonzero(flagged_all)[0][:4096])
-    ref, ref_st = oracle.solve(a[:, chk], deg[chk])
+    ref, ref_st = oracle.solve(a[:, chk], deg[chk], flags=OW)
     rs = to_host(r[:, torch.from_numpy(chk).to(r.device)])
     m = match_mixed(rs, ref, deg[chk])
     v = valid_mask(6, deg[chk], chk.size)
@@ -105,7 +109,7 @@ def test_known_roots_full_forward_and_backward():
     # backward at full size on the oracle's roots; loss sum |r - t|^2 with
     # each root paired to its nearest generating root (gap >= 0.05)
     _say("oracle on all 4M polynomials")
-    ref, _ = oracle.solve(coeffs)
+    ref, _ = oracle.solve(coeffs, flags=OW)
     near = np.argmin(np.abs(ref[:, None, :] - roots_true[None, :, :]), axis=1)
     tgt = np.take_along_axis(targets, near, axis=0)
     grad_r = 2.0 * (ref - tgt)
@@ -127,13 +131,14 @@ def test_clustered_full_classes_and_image():
     r32, s32 = pr.solve(c, None, "fp32_polish", max_iter_per_level=30)
     torch.cuda.synchronize()
     s64h, s32h = to_host(s64), to_host(s32)
-    # Triple clusters converge linearly; with 30 steps per level about 0.07%
-    # of them hit the cap in FP64, on the oracle as on the GPU.
+    # Triple clusters converge linearly: with Alg. 1's shift about 0.07% of
+    # them hit the cap of 30 steps per level in FP64; with the default
+    # (Wilkinson) shift next to none do, on the oracle as on the GPU.
     nc64 = (s64h & pr.ST_NOT_CONVERGED) != 0
     assert (s64h & ~pr.ST_NOT_CONVERGED).max() == 0
     flagged = (s32h & pr.ST_POLISH_UNCONVERGED) != 0
     idx = _sample(n, 32768, seed=3)
-    ref, ref_st = oracle.solve(coeffs[:, idx])
+    ref, ref_st = oracle.solve(coeffs[:, idx], flags=OW)
     onc = (ref_st & oracle.ST_NOT_CONVERGED) != 0
     _say(f"NOT_CONVERGED: gpu {nc64.mean():.2e} of all, oracle {onc.mean():.2e} of the sample")
     assert nc64.mean() < 2e-3 and abs(nc64.mean() - onc.mean()) < 1e-3

@@ -22,6 +22,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 pr = pytest.importorskip("paper_2507_02164_amd")
 
+# the oracle with the library's default shift (Wilkinson's); tests of Alg. 1's
+# shift pass PR_FLAG_RAYLEIGH_SHIFT to the library and no flag to the oracle
+OW = oracle.FLAG_WILKINSON_SHIFT
+
 
 def _solve(a, deg=None, precision="fp64", **kw):
     kw.setdefault("max_iter_per_level", 30)   # the oracle's cap
@@ -57,7 +61,7 @@ def test_gaussian_full(precision):
     """65,536 monic degree-6 polynomials with standard complex normal
     coefficients, every root."""
     a = workloads.gaussian(65536, seed=0)
-    ref, ref_st = oracle.solve(a)
+    ref, ref_st = oracle.solve(a, flags=OW)
     got, st = _solve(a, None, precision)
     assert np.all(ref_st == 0)
     if precision == "fp64":
@@ -73,7 +77,7 @@ def test_gaussian_full(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
 def test_parametric_grid(precision):
     a = workloads.parametric(256, seed=0)
-    ref, ref_st = oracle.solve(a)
+    ref, ref_st = oracle.solve(a, flags=OW)
     got, st = _solve(a, None, precision)
     worst, flagged = _check_roots(got, st, a, None, ref, ref_st, flagged_ok=precision != "fp64")
     assert flagged < 1e-3
@@ -84,7 +88,7 @@ def test_mixed_degree(precision):
     """Degrees 2..6 in one batch, log-uniform moduli; FP32 + polish within
     1e-8 of the FP64 oracle on every polynomial."""
     a, deg = workloads.mixed(50000, seed=3)
-    ref, ref_st = oracle.solve(a, deg)
+    ref, ref_st = oracle.solve(a, deg, flags=OW)
     got, st = _solve(a, deg, precision)
     floor = 1e-10 if precision == "fp64" else 1e-8
     worst, flagged = _check_roots(got, st, a, deg, ref, ref_st, floor=floor,
@@ -110,7 +114,7 @@ def test_clustered_classes():
     the rounding floor kappa u; the isolated roots and the cluster centroid
     stay within 1e-9.  FP32 + polish flags (nearly) every cluster."""
     coeffs, roots = workloads.clustered(8192, seed=0)
-    ref, ref_st = oracle.solve(coeffs)
+    ref, ref_st = oracle.solve(coeffs, flags=OW)
     got, st = _solve(coeffs, None, "fp64")
     kappa = rel_condition(coeffs, ref)
     m = match(got, ref)
@@ -128,7 +132,7 @@ def test_clustered_classes():
 @pytest.mark.parametrize("n", [1, 7, 255, 257, 1000])
 def test_ragged_sizes(n):
     a = workloads.gaussian(n, seed=n)
-    ref, _ = oracle.solve(a)
+    ref, _ = oracle.solve(a, flags=OW)
     for precision in ("fp64", "fp32_polish"):
         got, st = _solve(a, None, precision)
         assert got.shape == (6, n)
@@ -141,7 +145,7 @@ def test_smaller_dmax(dmax):
     n = 3000
     a = (rng.standard_normal((dmax + 1, n)) + 1j * rng.standard_normal((dmax + 1, n))) / np.sqrt(2)
     deg = rng.integers(1, dmax + 1, n).astype(np.int32)
-    ref, ref_st = oracle.solve(a, deg)
+    ref, ref_st = oracle.solve(a, deg, flags=OW)
     for precision in ("fp64", "fp32_polish"):
         got, st = _solve(a, deg, precision)
         assert np.array_equal(st & 0x7, ref_st & 0x7)
@@ -154,7 +158,7 @@ def test_invalid_inputs_and_flags():
     a[2, 3] = np.nan
     a[6, 4] = 0.0
     a[1, 7] = np.inf
-    ref, ref_st = oracle.solve(a, deg)
+    ref, ref_st = oracle.solve(a, deg, flags=OW)
     for precision in ("fp64", "fp32_polish"):
         got, st = _solve(a, deg, precision)
         np.testing.assert_array_equal(st.astype(np.uint32) & 0x7, ref_st)
@@ -174,17 +178,21 @@ def test_special_polynomials():
             cols.append(w)
     a = np.stack(cols, axis=1)
     deg = np.array([int(np.nonzero(a[:, i])[0].max()) for i in range(a.shape[1])], dtype=np.int32)
-    ref, ref_st = oracle.solve(a, deg)
+    ref, ref_st = oracle.solve(a, deg, flags=OW)
     got, st = _solve(a, deg, "fp64")
     assert np.all(st == 0) and np.all(ref_st == 0)
     m = match_mixed(got, ref, deg)
     v = valid_mask(6, deg, a.shape[1])
     assert np.abs(m - ref)[v].max() < 1e-14 * 4
-    # with the exceptional shift off, z^d - c stalls and is flagged
-    got, st = _solve(a, deg, "fp64", flags=pr.FLAG_NO_EXCEPTIONAL_SHIFT)
-    _, ost = oracle.solve(a, deg, flags=oracle.FLAG_NO_EXCEPTIONAL_SHIFT)
-    np.testing.assert_array_equal(st.astype(np.uint32) & pr.ST_NOT_CONVERGED, ost & pr.ST_NOT_CONVERGED)
-    assert (st & pr.ST_NOT_CONVERGED).sum() > 0
+    # with the exceptional shift off, z^d - c stalls and is flagged: with
+    # Alg. 1's shift at every degree, with Wilkinson's (the default) from
+    # degree 3 on (its 2 x 2 block [[0, 0], [1, 0]] gives the same shift 0)
+    for gflags, oflags in ((pr.FLAG_RAYLEIGH_SHIFT, 0), (0, oracle.FLAG_WILKINSON_SHIFT)):
+        got, st = _solve(a, deg, "fp64", flags=pr.FLAG_NO_EXCEPTIONAL_SHIFT | gflags)
+        _, ost = oracle.solve(a, deg, flags=oracle.FLAG_NO_EXCEPTIONAL_SHIFT | oflags)
+        np.testing.assert_array_equal(st.astype(np.uint32) & pr.ST_NOT_CONVERGED,
+                                      ost & pr.ST_NOT_CONVERGED)
+        assert (st & pr.ST_NOT_CONVERGED).sum() > 0
     # a cap of one step per level flags (nearly) everything, host-forced
     g = workloads.gaussian(512, seed=2)
     got, st = _solve(g, None, "fp64", max_iter_per_level=1)
@@ -193,7 +201,7 @@ def test_special_polynomials():
 
 def test_non_monic():
     a = workloads.gaussian(20000, seed=4) * (0.3 - 2.1j)
-    ref, _ = oracle.solve(a)
+    ref, _ = oracle.solve(a, flags=OW)
     for precision in ("fp64", "fp32_polish"):
         got, st = _solve(a, None, precision)
         _check_roots(got, st, a, None, ref, np.zeros(a.shape[1], np.uint32),
@@ -210,17 +218,20 @@ def test_vieta_trace_on_gpu():
 
 
 def test_iteration_counts_distribution():
-    """Exact per-level counts depend on rounding (parity unpinned); their
-    distribution must match the oracle's, and z^d deflates in one step."""
+    """Alg. 1's shift (PR_FLAG_RAYLEIGH_SHIFT): exact per-level counts depend
+    on rounding (parity unpinned); their distribution must match the
+    oracle's, and z^d deflates in one step.  The default shift's counts are
+    checked with its own tests."""
     a = workloads.gaussian(65536, seed=0)
     _, _, oit = oracle.solve(a, return_iters=True)
-    got, st, it = _solve(a, None, "fp64", iter_counts=True)
+    got, st, it = _solve(a, None, "fp64", iter_counts=True, flags=pr.FLAG_RAYLEIGH_SHIFT)
     assert it.shape == (5, 65536)
     assert np.abs(it.mean(axis=1) - oit.mean(axis=1)).max() < 0.05 * oit.mean(axis=1).max()
     assert (it == oit).mean() > 0.9
     z = np.zeros((7, 4), dtype=np.complex128); z[6] = 1.0
-    _, _, zit = _solve(z, None, "fp64", iter_counts=True)
-    assert np.all(zit == 1)
+    for flags in (pr.FLAG_RAYLEIGH_SHIFT, 0):
+        _, _, zit = _solve(z, None, "fp64", iter_counts=True, flags=flags)
+        assert np.all(zit == 1)
 
 
 def test_deterministic():
@@ -233,7 +244,7 @@ def test_deterministic():
 
 def test_stream_and_out_buffers():
     a = workloads.gaussian(4096, seed=6)
-    ref, _ = oracle.solve(a)
+    ref, _ = oracle.solve(a, flags=OW)
     s = torch.cuda.Stream()
     ca = to_dev(a)
     roots = torch.empty((6, 4096), dtype=torch.complex128, device=ca.device)
@@ -259,7 +270,7 @@ def test_tiled_equals_flat(precision):
         got = _solve(a, deg, precision, tile=tile, grid_blocks=grid, iter_counts=True)
         for x, y in zip(got, flat):
             assert np.array_equal(x, y, equal_nan=True), (tile, grid)
-    ref, ref_st = oracle.solve(a, deg)
+    ref, ref_st = oracle.solve(a, deg, flags=OW)
     np.testing.assert_array_equal(flat[1].astype(np.uint32) & 0x7, ref_st & 0x7)
 
 
@@ -290,7 +301,7 @@ def test_fixed_steps_mode_matches_oracle_and_paper_counts(precision):
         assert np.median(err) < 1e-14
     else:
         # the polish takes the fixed-T FP32 roots to the converged roots
-        conv, _ = oracle.solve(a)
+        conv, _ = oracle.solve(a, flags=OW)
         ok = (st & pr.ST_POLISH_UNCONVERGED) == 0
         err = rel_err(match(got[:, ok], conv[:, ok]), conv[:, ok])
         assert ok.mean() > 0.95 and np.quantile(err, 0.99) < 1e-10
