@@ -116,8 +116,9 @@ def cpu_baseline(coeffs_host, target_s=10.0):
 
 
 def bench_mixed(args, torch, workloads, pr, dev):
-    """Mixed degrees 2..6: one persistent degree-sorted launch against the
-    index-order launch, FP32 + polish, solve only."""
+    """Mixed degrees 2..6, solve only, both forms: the persistent
+    degree-sorted launch (autotuned layout) against the index-order launch,
+    and the former captured in a HIP graph and replayed."""
     n = 64 * 2 ** 20
     log(f"generating {n} mixed-degree polynomials")
     a_host, deg_host = workloads.mixed(n, seed=0)
@@ -142,6 +143,27 @@ def bench_mixed(args, torch, workloads, pr, dev):
             ms = e0.elapsed_time(e1) / args.steps
             out[f"{form}_{layout}"] = {"solve_ms": ms, "polys_per_s": n / (ms * 1e-3)}
             log(f"{form} {layout}: {ms:.3f} ms/solve, {n / (ms * 1e-3):.3e} polys/s")
+        # the same autotuned persistent launch captured once into a HIP graph
+        # and replayed
+        from paper_2507_02164_amd.graph import PathGraph
+        g = PathGraph(a, deg, form)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        st = g.status
+        out[f"{form}_graph"] = {"solve_ms": ms, "polys_per_s": n / (ms * 1e-3),
+                                "not_converged": int(((st & pr.ST_NOT_CONVERGED) != 0).sum()),
+                                "polish_unconverged": int(((st & pr.ST_POLISH_UNCONVERGED) != 0).sum())}
+        log(f"{form} graph replay: {ms:.3f} ms/solve, {n / (ms * 1e-3):.3e} polys/s")
+        del g
     print(json.dumps({"workload": "mixed degrees 2..6, 64Mi polynomials", "n": n, "results": out}))
 
 
