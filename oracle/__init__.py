@@ -16,7 +16,9 @@ What each function follows in arXiv 2507.02164:
                fixed iteration count (``fixed_t`` reproduces Alg. 2), and,
                with ``FLAG_WILKINSON_SHIFT``, Wilkinson's shift (the
                eigenvalue of the trailing 2 x 2 block nearest its bottom
-               entry) in place of Alg. 1's bottom-right entry.
+               entry) in place of Alg. 1's bottom-right entry; with
+               ``FLAG_QUADRATIC_START`` the first step of each polynomial is
+               shifted by the root nearest 0 of b0 + b1 z + b2 z^2.
   density   -- Sec. III, roots converted to pixel coordinates and counted.
   backward  -- not in the paper: the implicit-function derivative
                dr/da_k = -r^k / p'(r) of a simple root.
@@ -41,6 +43,7 @@ ST_SINGULAR_DERIV = 0x20
 
 FLAG_NO_EXCEPTIONAL_SHIFT = 0x1
 FLAG_WILKINSON_SHIFT = 0x8
+FLAG_QUADRATIC_START = 0x10
 
 _lib = None
 
@@ -82,6 +85,8 @@ def _load():
         lib.oracle_qr_step.restype = None
         lib.oracle_wilkinson_shift.argtypes = [P, P, P, P, P]
         lib.oracle_wilkinson_shift.restype = None
+        lib.oracle_quadratic_start.argtypes = [P, P, P, P]
+        lib.oracle_quadratic_start.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -233,6 +238,15 @@ def wilkinson_shift(a: complex, b: complex, c: complex, e: complex) -> complex:
     mu = np.zeros(2)
     _load().oracle_wilkinson_shift(*(_ptr(x) for x in v), _ptr(mu))
     return complex(mu[0], mu[1])
+
+
+def quadratic_start(b0: complex, b1: complex, b2: complex):
+    """The root nearest 0 of b0 + b1 z + b2 z^2 and whether it is defined
+    (the first shift taken with ``FLAG_QUADRATIC_START``)."""
+    v = [np.array([z.real, z.imag]) for z in (complex(b0), complex(b1), complex(b2))]
+    z = np.zeros(2)
+    ok = _load().oracle_quadratic_start(*(_ptr(x) for x in v), _ptr(z))
+    return complex(z[0], z[1]), bool(ok)
 
 
 def qr_step(H, shift: complex):

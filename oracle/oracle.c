@@ -47,7 +47,13 @@
  *     eigenvalue of the trailing 2 x 2 block nearest that entry (Wilkinson's
  *     shift, the textbook choice for single-shift QR; not in the paper).
  *     It is still one complex shift per QR step; only its value changes.
- *     The fixed-T mode, being Alg. 2 literally, keeps Alg. 1's shift.
+ *     The fixed-T mode, being Alg. 2 literally, keeps Alg. 1's shift;
+ *   - an optional first shift (flag, not in the paper): the very first QR
+ *     step of a polynomial is shifted by the root nearest 0 of
+ *     b_0 + b_1 z + b_2 z^2, an estimate of the smallest root, which the
+ *     first unshifted steps would otherwise isolate slowly (the trailing
+ *     block of the companion matrix is [[0, 0], [1, 0]], so both Alg. 1's and
+ *     Wilkinson's first shift is 0).  Not in the fixed-T mode either.
  */
 #include <complex.h>
 #include <math.h>
@@ -71,6 +77,7 @@
 #define OFLAG_NO_EXCEPTIONAL_SHIFT 0x1u
 #define OFLAG_FIXED_T 0x2u
 #define OFLAG_WILKINSON_SHIFT 0x8u
+#define OFLAG_QUADRATIC_START 0x10u
 
 #define ODMAX 6
 
@@ -174,6 +181,44 @@ static cplx wilkinson_shift(cplx a, cplx b, cplx c, cplx e)
     return e - bc / den;
 }
 
+/* The root nearest 0 of b0 + b1 z + b2 z^2 (b2 != 0 or b1 != 0): with
+ * D = sqrt(b1^2 - 4 b0 b2) the roots are 2 b0 / (-b1 -+ D) (the product of
+ * the two roots of the quadratic is b0 / b2, and this form needs no b2 in a
+ * denominator); of the two denominators the one of larger modulus gives the
+ * smaller root.  Returns 0 (and *ok = 0) where that denominator is zero
+ * (b0 == b1 == 0 with b2 == 0, or a double root at 0 -- then 0 is the
+ * root) and *ok = 0 where the value is not finite. */
+static cplx quadratic_start(cplx b0, cplx b1, cplx b2, int *ok)
+{
+    cplx d = csqrt(b1 * b1 - 4.0 * b0 * b2);
+    cplx den1 = -b1 - d, den2 = -b1 + d;
+    cplx den = cabs(den1) >= cabs(den2) ? den1 : den2;
+    *ok = 1;
+    if (den == 0.0) {
+        *ok = b0 == 0.0;
+        return 0.0;
+    }
+    cplx z = 2.0 * b0 / den;
+    if (!cfinite(z)) {
+        *ok = 0;
+        return 0.0;
+    }
+    return z;
+}
+
+/* Exposed for tests: the quadratic start of b0 + b1 z + b2 z^2; returns
+ * whether it is defined. */
+int oracle_quadratic_start(const double *b0_ri, const double *b1_ri, const double *b2_ri,
+                           double *z_ri)
+{
+    int ok;
+    cplx z = quadratic_start(b0_ri[0] + I * b0_ri[1], b1_ri[0] + I * b1_ri[1],
+                             b2_ri[0] + I * b2_ri[1], &ok);
+    z_ri[0] = creal(z);
+    z_ri[1] = cimag(z);
+    return ok;
+}
+
 /* Exposed for tests: Wilkinson's shift of [[a, b], [c, e]], each complex
  * value as interleaved (re, im) doubles. */
 void oracle_wilkinson_shift(const double *a_ri, const double *b_ri, const double *c_ri,
@@ -250,6 +295,12 @@ static unsigned solve_one(int d, const cplx *a, cplx *eig, int *its_out,
             if ((flags & OFLAG_WILKINSON_SHIFT) && fixed_t <= 0)
                 s = wilkinson_shift(H[(m - 2) * d + (m - 2)], H[(m - 2) * d + (m - 1)], hsub,
                                     H[(m - 1) * d + (m - 1)]);
+            if ((flags & OFLAG_QUADRATIC_START) && fixed_t <= 0 && m == d && its == 0) {
+                int ok;
+                cplx z = quadratic_start(b[0], b[1], d >= 3 ? b[2] : 1.0, &ok);
+                if (ok)
+                    s = z;
+            }
             if (fixed_t <= 0 && !(flags & OFLAG_NO_EXCEPTIONAL_SHIFT) && (its == 10 || its == 20))
                 s += cabs1(hsub) * (0.75 + 0.5 * I);
             qr_step(m, d, H, s);
