@@ -36,6 +36,10 @@ if ROOT not in sys.path:
 # root per Newton step at degree d.
 F_LEVEL = {2: 131, 3: 314, 4: 553, 5: 848, 6: 1199}
 F_WILKINSON = 36
+# the default rule's first shift, once per polynomial: b1^2 - 4 b0 b2 10,
+# |q| 4, the square root's two parts 6, side test 3, denominator 2, its norm
+# 3, 2 b0 conj(den) / |den|^2 8
+F_START = 36
 PEAK_FP64 = 78.6e12          # MI355X vector FP64, FLOP/s
 PEAK_FP32 = 157.3e12         # MI355X vector FP32 (published)
 PEAK_HBM = 8.0e12            # B/s
@@ -83,12 +87,13 @@ def lockstep_flops(iters, wave=64, shift=F_WILKINSON):
     return tot
 
 
-def algorithmic_flops(iters, shift=F_WILKINSON):
+def algorithmic_flops(iters, shift=F_WILKINSON, start=F_START):
     """Sum over polynomials and levels of steps x (F(m) + the shift's own
-    FLOPs: F_WILKINSON for the default shift, 0 for Alg. 1's bottom entry).
-    iters [5, n] int."""
+    FLOPs: F_WILKINSON for the default rule, 0 for Alg. 1's bottom entry),
+    plus the default rule's first shift once per polynomial.  iters [5, n]."""
     it = iters.astype(np.float64)
-    return float(sum(it[m - 2].sum() * (F_LEVEL[m] + shift) for m in range(2, 7)))
+    return float(sum(it[m - 2].sum() * (F_LEVEL[m] + shift) for m in range(2, 7))
+                 + start * it.shape[1])
 
 
 def cpu_baseline(coeffs_host, target_s=10.0):
@@ -96,8 +101,8 @@ def cpu_baseline(coeffs_host, target_s=10.0):
     threads = oracle.max_threads()
     n_total = coeffs_host.shape[1]
     probe = min(65536, n_total)
-    # the same method as the GPU path: Wilkinson's shift
-    flags = oracle.FLAG_WILKINSON_SHIFT
+    # the same method as the GPU path: Wilkinson's shift, quadratic start
+    flags = oracle.FLAG_WILKINSON_SHIFT | oracle.FLAG_QUADRATIC_START
     t0 = time.perf_counter()
     oracle.solve(coeffs_host[:, :probe], flags=flags)
     dt = time.perf_counter() - t0
@@ -110,7 +115,7 @@ def cpu_baseline(coeffs_host, target_s=10.0):
     return {
         "value": n / dt, "unit": "polys/s", "cores": threads, "kind": "oracle",
         "sample": f"first {n} polynomials of the same grid (rows 0..{(n - 1) // 4096} of 4096), "
-                  f"FP64 oracle solve only, Wilkinson shift as on the GPU, {dt:.1f} s",
+                  f"FP64 oracle solve only, shift rule as on the GPU, {dt:.1f} s",
         "host_cpu": platform.processor() or platform.machine(),
     }, roots, n
 
@@ -388,7 +393,7 @@ def main():
                          mean_qr_steps=float(its_h.sum(axis=0).mean()),
                          flagged_frac=float((st_h != 0).mean()),
                          alg_tflops=flops / (fused_ms * 1e-3) / 1e12,
-                         lockstep_efficiency=algorithmic_flops(its_h) / lockstep_flops(its_h),
+                         lockstep_efficiency=algorithmic_flops(its_h, start=0) / lockstep_flops(its_h),
                          executed_sweep_tflops=lockstep_flops(its_h) / (fused_ms * 1e-3) / 1e12)
         log(f"{form}: step {step_ms:.3f} ms, solve+bin {fused_ms:.3f} ms, "
             f"backward {back_ms:.3f} ms")
@@ -450,7 +455,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ray_ms = e0.elapsed_time(e1) / args.steps
-        fl_r = algorithmic_flops(its_r, shift=0) + (n * polish_flops(6, 2)
+        fl_r = algorithmic_flops(its_r, shift=0, start=0) + (n * polish_flops(6, 2)
                                                     if form == "fp32_polish" else 0)
         res[form]["paper_shift"] = dict(
             zero_and_solve_bin_ms=ray_ms, mean_qr_steps=float(its_r.sum(axis=0).mean()),

@@ -261,6 +261,15 @@ __device__ __forceinline__ double sqrt_t(double x)
 {
     return x > 0.0 ? x * rsqrt_t(x) : 0.0;  // x == +inf gives NaN: not finite, as wanted
 }
+// Reciprocal for a shift's value (accuracy of a few ulp is plenty): the
+// hardware estimate, refined once in FP64.  0 gives +inf, which the callers
+// reject as not finite.
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x)
+{
+    const double y0 = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(y0, __builtin_fma(-x, y0, 1.0), y0);
+}
 template <typename T>
 __device__ __forceinline__ cx<T> wilkinson(cx<T> a, cx<T> b, cx<T> c, cx<T> e)
 {
@@ -276,6 +285,37 @@ __device__ __forceinline__ cx<T> wilkinson(cx<T> a, cx<T> b, cx<T> c, cx<T> e)
     rr = pick(flip, -rr, rr);
     ri = pick(flip, -ri, ri);
     return {e.re + T(0.5) * (dr - rr), e.im + T(0.5) * (di - ri)};
+}
+
+// First shift of a polynomial (default shift rule): the root nearest 0 of
+// b0 + b1 z + b2 z^2, b the monic coefficients, an estimate of the smallest
+// root -- the eigenvalue the first unshifted steps would isolate slowly (the
+// trailing block of the companion matrix is [[0, 0], [1, 0]], so the
+// bottom-entry and Wilkinson shifts both start at 0).  The roots are
+// 2 b0 / (-b1 -+ D), D^2 = b1^2 - 4 b0 b2; the denominator of larger modulus,
+// -b1 - D with Re(conj(b1) D) >= 0, gives the smaller root.  D is taken as in
+// `wilkinson`.  ok is false where the denominator is zero or the value is
+// not finite; the caller then keeps the other shift (0 at this point, the
+// root when b0 == 0).
+template <typename T>
+__device__ __forceinline__ cx<T> quad_start(cx<T> b0, cx<T> b1, cx<T> b2, bool& ok)
+{
+    const T qr = b1.re * b1.re - b1.im * b1.im - T(4) * (b0.re * b2.re - b0.im * b2.im);
+    const T qi = T(2) * b1.re * b1.im - T(4) * (b0.re * b2.im + b0.im * b2.re);
+    const T u = (sqrt_t(qr * qr + qi * qi) + __builtin_fabs(qr)) * T(0.5);
+    const T iw = pick(u > T(0), rsqrt_t(u), T(0));
+    const T w = u * iw, v = qi * T(0.5) * iw;
+    const bool pos = qr >= T(0);
+    T dr = pick(pos, w, v), di = pick(pos, v, w);
+    const bool flip = b1.re * dr + b1.im * di < T(0);
+    dr = pick(flip, -dr, dr);
+    di = pick(flip, -di, di);
+    const T er = -b1.re - dr, ei = -b1.im - di;
+    const T n = er * er + ei * ei;
+    const T g = T(2) * rcp_t(n);
+    const cx<T> z = {(b0.re * er + b0.im * ei) * g, (b0.im * er - b0.re * ei) * g};
+    ok = n > T(0) && __builtin_isfinite(z.re) && __builtin_isfinite(z.im);
+    return z;
 }
 
 template <typename T>
@@ -295,8 +335,8 @@ struct Eps<float> {
 // to level M-1.  Every other lane at level M takes one shifted QR step; lanes
 // below level M ride along with the identity.
 template <typename T, int DM, int M, typename Emit>
-__device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int cap, bool exc,
-                                     bool fixed, bool wilk, uint32_t& st,
+__device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int d, int cap,
+                                     bool exc, bool fixed, bool wilk, uint32_t& st,
                                      int32_t* __restrict__ iters, int64_t n, int64_t i,
                                      Emit&& emit)
 {
@@ -322,6 +362,21 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int c
         const cx<T> w = wilkinson(h[M - 2][M - 2], h[M - 2][M - 1], h[M - 1][M - 2], mu);
         const bool fin = __builtin_isfinite(w.re) && __builtin_isfinite(w.im);
         mu = {pick(fin, w.re, mu.re), pick(fin, w.im, mu.im)};
+        // the polynomial's first step: its companion row is untouched (the
+        // identity steps of the levels above keep values), h[0][M-1-k] =
+        // -b_k of the (scaled) monic polynomial
+        const bool first = here && its == 0 && d == M;
+        if (__ballot(first)) {  // wave-uniform
+            const cx<T> b0 = {-h[0][M - 1].re, -h[0][M - 1].im};
+            const cx<T> b1 = {-h[0][M - 2].re, -h[0][M - 2].im};
+            cx<T> b2 = {T(1), T(0)};
+            if constexpr (M >= 3)
+                b2 = {-h[0][M - 3].re, -h[0][M - 3].im};
+            bool ok;
+            const cx<T> z = quad_start(b0, b1, b2, ok);
+            const bool take = first && ok;
+            mu = {pick(take, z.re, mu.re), pick(take, z.im, mu.im)};
+        }
     }
     const cx<T> sh = {pick(act, pick(ex, ere, mu.re), T(0)),
                       pick(act, pick(ex, eim, mu.im), T(0))};
@@ -343,19 +398,19 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int c
 // copies back at the loop edge cost both instructions and, above all,
 // registers; over two trips the register assignment closes up.
 template <typename T, int DM, int M, typename Emit>
-__device__ __forceinline__ void iterate_from(cx<T> (&h)[DM][DM], int& m, int& its, int cap,
+__device__ __forceinline__ void iterate_from(cx<T> (&h)[DM][DM], int& m, int& its, int d, int cap,
                                              bool exc, bool fixed, bool wilk, uint32_t& st,
                                              int32_t* __restrict__ iters, int64_t n, int64_t i,
                                              Emit&& emit)
 {
     if constexpr (M >= 2) {
         while (__ballot(m == M)) {
-            trip<T, DM, M>(h, m, its, cap, exc, fixed, wilk, st, iters, n, i, emit);
+            trip<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
             if (!__ballot(m == M))
                 break;
-            trip<T, DM, M>(h, m, its, cap, exc, fixed, wilk, st, iters, n, i, emit);
+            trip<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
         }
-        iterate_from<T, DM, M - 1>(h, m, its, cap, exc, fixed, wilk, st, iters, n, i, emit);
+        iterate_from<T, DM, M - 1>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
     }
 }
 
@@ -366,7 +421,7 @@ __device__ __forceinline__ void iterate(cx<T> (&h)[DM][DM], int d, int cap, bool
                                         Emit&& emit)
 {
     int m = d, its = 0;
-    iterate_from<T, DM, DM>(h, m, its, cap, exc, fixed, wilk, st, iters, n, i, emit);
+    iterate_from<T, DM, DM>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
 }
 
 // Companion matrix, first-row form: h[0][j] = -b_{d-1-j} for j < d, ones on

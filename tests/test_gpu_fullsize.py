@@ -20,9 +20,10 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
 pr = pytest.importorskip("paper_2507_02164_amd")
 
-# the oracle with the library's default shift (Wilkinson's); tests of Alg. 1's
-# shift pass PR_FLAG_RAYLEIGH_SHIFT to the library and no flag to the oracle
-OW = oracle.FLAG_WILKINSON_SHIFT
+# the oracle with the library's default shift rule (Wilkinson's shift, the
+# first step from the quadratic start); tests of Alg. 1's shift pass
+# PR_FLAG_RAYLEIGH_SHIFT to the library and no flag to the oracle
+OW = oracle.FLAG_WILKINSON_SHIFT | oracle.FLAG_QUADRATIC_START
 
 
 def _say(msg):

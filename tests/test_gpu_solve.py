@@ -22,9 +22,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 pr = pytest.importorskip("paper_2507_02164_amd")
 
-# the oracle with the library's default shift (Wilkinson's); tests of Alg. 1's
-# shift pass PR_FLAG_RAYLEIGH_SHIFT to the library and no flag to the oracle
-OW = oracle.FLAG_WILKINSON_SHIFT
+# the oracle with the library's default shift rule (Wilkinson's shift, the
+# first step from the quadratic start); tests of Alg. 1's shift pass
+# PR_FLAG_RAYLEIGH_SHIFT to the library and no flag to the oracle
+OW = oracle.FLAG_WILKINSON_SHIFT | oracle.FLAG_QUADRATIC_START
 
 
 def _solve(a, deg=None, precision="fp64", **kw):
@@ -187,7 +188,7 @@ def test_special_polynomials():
     # with the exceptional shift off, z^d - c stalls and is flagged: with
     # Alg. 1's shift at every degree, with Wilkinson's (the default) from
     # degree 3 on (its 2 x 2 block [[0, 0], [1, 0]] gives the same shift 0)
-    for gflags, oflags in ((pr.FLAG_RAYLEIGH_SHIFT, 0), (0, oracle.FLAG_WILKINSON_SHIFT)):
+    for gflags, oflags in ((pr.FLAG_RAYLEIGH_SHIFT, 0), (0, OW)):
         got, st = _solve(a, deg, "fp64", flags=pr.FLAG_NO_EXCEPTIONAL_SHIFT | gflags)
         _, ost = oracle.solve(a, deg, flags=oracle.FLAG_NO_EXCEPTIONAL_SHIFT | oflags)
         np.testing.assert_array_equal(st.astype(np.uint32) & pr.ST_NOT_CONVERGED,

@@ -1,12 +1,14 @@
-"""GPU parity of pr_solve's default shift -- Wilkinson's, the eigenvalue of
-the trailing 2 x 2 block nearest its bottom entry -- against the oracle with
-FLAG_WILKINSON_SHIFT (run on an MI355X); PR_FLAG_RAYLEIGH_SHIFT selects
-Alg. 1's bottom-entry shift, which the other solve tests pin.
+"""GPU parity of pr_solve's default shift rule -- Wilkinson's shift (the
+eigenvalue of the trailing 2 x 2 block nearest its bottom entry), the first
+step of each polynomial shifted by the root nearest 0 of b0 + b1 z + b2 z^2
+-- against the oracle with FLAG_WILKINSON_SHIFT | FLAG_QUADRATIC_START (run
+on an MI355X); PR_FLAG_RAYLEIGH_SHIFT selects Alg. 1's bottom-entry shift,
+which the other solve tests pin.
 
-The kernels evaluate the shift without the oracle's division (see the
-shift's definition in the solve kernel), so the two sides round differently
-and exact per-level step counts are not pinned; their distribution is, and
-the roots are held to the same bounds as with Alg. 1's shift."""
+The kernels evaluate the shifts without the oracle's divisions (see their
+definitions in the solve kernel), so the two sides round differently and
+exact per-level step counts are not pinned; their distribution is, and the
+roots are held to the same bounds as with Alg. 1's shift."""
 from __future__ import annotations
 
 import numpy as np
@@ -22,7 +24,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 pr = pytest.importorskip("paper_2507_02164_amd")
 
-W = oracle.FLAG_WILKINSON_SHIFT
+W = oracle.FLAG_WILKINSON_SHIFT | oracle.FLAG_QUADRATIC_START
 R = pr.FLAG_RAYLEIGH_SHIFT
 
 
