@@ -31,15 +31,17 @@
 //   * Convergence (the paper uses a fixed count): level m deflates once
 //     cabs1(h[m-1][m-2]) <= eps (cabs1(h[m-1][m-1]) + cabs1(h[m-2][m-2])),
 //     evaluated in FP64, eps = 2^-52 for FP64 sweeps and 2^-23 for FP32
-//     sweeps.  Exceptional shift s += cabs1(h[m-1][m-2]) (0.75 + 0.5i) on the
-//     10th and 20th step of a level; after `cap` steps the level deflates
-//     anyway and NOT_CONVERGED is set.
+//     sweeps.  Exceptional shift s = h[m-1][m-1] + cabs1(h[m-1][m-2])
+//     (0.75 + 0.5i) on the 10th and 20th step of a level; after `cap` steps
+//     the level deflates anyway and NOT_CONVERGED is set.
 //   * Shift (the paper takes the bottom-right entry): by default the
 //     eigenvalue of the trailing 2 x 2 block nearest that entry (Wilkinson's
 //     shift; still one complex shift per step, only its value differs: about
 //     45 more instructions per step and a fifth fewer steps per polynomial,
-//     a 2 x 2 block deflating in one).  PR_FLAG_RAYLEIGH_SHIFT and the
-//     fixed-step mode take the bottom-right entry.
+//     a 2 x 2 block deflating in one), and, on each polynomial's very first
+//     step, the root nearest 0 of b0 + b1 z + b2 z^2 (both rules would start
+//     from 0).  PR_FLAG_RAYLEIGH_SHIFT and the fixed-step mode take the
+//     bottom-right entry throughout.
 //   * FP32 form: sweeps in FP32, test in FP64, then every root is polished
 //     by Newton steps r <- r - p(r)/p'(r) in FP64 on the original
 //     coefficients.
