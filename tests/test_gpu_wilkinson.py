@@ -76,10 +76,17 @@ def test_parametric_slice_fp32_polish():
 @pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
 def test_mixed_degrees(precision):
     a, deg = workloads.mixed(100_000, seed=32)
-    ref, ref_st = oracle.solve(a, deg, flags=W)
+    ref, ref_st, oit = oracle.solve(a, deg, flags=W, return_iters=True)
     for tile in (-1, 512):
-        got, st = _solve(a, deg, precision, tile=tile)
+        got, st, it = _solve(a, deg, precision, tile=tile, iter_counts=True)
         _parity(got, st, a, deg, ref, ref_st, floor=1e-10 if precision == "fp64" else 1e-8)
+        if precision == "fp64":
+            # every lane takes the quadratic start at its own top level: the
+            # step counts of each degree's top level follow the oracle's
+            for d in range(2, 7):
+                sel = deg == d
+                assert abs(it[d - 2, sel].mean() - oit[d - 2, sel].mean()) < 0.05, d
+                assert (it[:, sel] == oit[:, sel]).mean() > 0.95, d
 
 
 @pytest.mark.parametrize("d", [2, 3, 4, 5, 6])
