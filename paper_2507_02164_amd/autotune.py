@@ -159,7 +159,9 @@ def main():
     samples = {
         False: (torch.from_numpy(workloads.parametric(2048, seed=0)).to(dev), None),
     }
-    a, d = workloads.mixed(8 * 2 ** 20, seed=0)
+    # the persistent grid's best size depends on the batch (work per block):
+    # the mixed-degree layouts are tuned at the size of the 64 Mi workload
+    a, d = workloads.mixed(64 * 2 ** 20, seed=0)
     samples[True] = (torch.from_numpy(a).to(dev), torch.from_numpy(d).to(dev))
     for mixed, (c, deg) in samples.items():
         for precision in ("fp32_polish", "fp64"):
