@@ -106,11 +106,14 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _check(t, name, dtype, shape=None):
+def _check(t, name, dtype, shape=None, device=None):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if device is not None and t.device != device:
+        # a pointer into another GPU's memory would be read by this GPU's kernel
+        raise ValueError(f"{name} must be on {device} like the other arrays, got {t.device}")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
@@ -134,14 +137,14 @@ def _prepare_solve(coeffs, degrees, precision, max_iter_per_level, polish_steps,
     n = coeffs.shape[1]
     dev = coeffs.device
     if degrees is not None:
-        _check(degrees, "degrees", torch.int32, (n,))
+        _check(degrees, "degrees", torch.int32, (n,), device=coeffs.device)
     if roots is None and want_roots:
         roots = torch.empty((max(dmax, 0), n), dtype=torch.complex128, device=dev)
     if roots is not None:
-        _check(roots, "roots", torch.complex128, (dmax, n))
+        _check(roots, "roots", torch.complex128, (dmax, n), device=coeffs.device)
     if status is None:
         status = torch.empty((n,), dtype=torch.int32, device=dev)
-    _check(status, "status", torch.int32, (n,))
+    _check(status, "status", torch.int32, (n,), device=coeffs.device)
     its = None
     if iter_counts:
         its = torch.empty((max(dmax - 1, 0), n), dtype=torch.int32, device=dev)
@@ -199,7 +202,7 @@ def solve_bin(coeffs, window, shape, degrees=None, precision="fp64", *, skip_mas
     width, height = (int(v) for v in shape)
     if out is None:
         out = torch.zeros((height, width), dtype=torch.int32, device=coeffs.device)
-    _check(out, "out", torch.int32, (height, width))
+    _check(out, "out", torch.int32, (height, width), device=coeffs.device)
     with torch.cuda.device(coeffs.device):
         rc = lib().pr_solve_bin(_ptr(coeffs), _ptr(degrees), n, dmax, _ptr(roots), _ptr(status),
                                 ctypes.byref(opts), skip_mask & 0xFFFFFFFF, x0, x1, y0, y1, width,
@@ -223,11 +226,11 @@ def density(roots, window, shape, degrees=None, status=None, skip_mask=0, out=No
     width, height = (int(v) for v in shape)
     if out is None:
         out = torch.zeros((height, width), dtype=torch.int32, device=roots.device)
-    _check(out, "out", torch.int32, (height, width))
+    _check(out, "out", torch.int32, (height, width), device=roots.device)
     if degrees is not None:
-        _check(degrees, "degrees", torch.int32, (n,))
+        _check(degrees, "degrees", torch.int32, (n,), device=roots.device)
     if status is not None:
-        _check(status, "status", torch.int32, (n,))
+        _check(status, "status", torch.int32, (n,), device=roots.device)
     with torch.cuda.device(roots.device):
         rc = lib().pr_density(_ptr(roots), _ptr(degrees), _ptr(status), skip_mask & 0xFFFFFFFF, n,
                               dmax, x0, x1, y0, y1, width, height, _ptr(out), _stream(stream))
@@ -244,16 +247,16 @@ def backward(coeffs, roots, grad_roots, degrees=None, status=None, grad_coeffs=N
     _check(coeffs, "coeffs", torch.complex128)
     dmax = coeffs.shape[0] - 1
     n = coeffs.shape[1]
-    _check(roots, "roots", torch.complex128, (dmax, n))
-    _check(grad_roots, "grad_roots", torch.complex128, (dmax, n))
+    _check(roots, "roots", torch.complex128, (dmax, n), device=coeffs.device)
+    _check(grad_roots, "grad_roots", torch.complex128, (dmax, n), device=coeffs.device)
     if degrees is not None:
-        _check(degrees, "degrees", torch.int32, (n,))
+        _check(degrees, "degrees", torch.int32, (n,), device=coeffs.device)
     if status is None:
         status = torch.zeros((n,), dtype=torch.int32, device=coeffs.device)
-    _check(status, "status", torch.int32, (n,))
+    _check(status, "status", torch.int32, (n,), device=coeffs.device)
     if grad_coeffs is None:
         grad_coeffs = torch.empty_like(coeffs)
-    _check(grad_coeffs, "grad_coeffs", torch.complex128, (dmax + 1, n))
+    _check(grad_coeffs, "grad_coeffs", torch.complex128, (dmax + 1, n), device=coeffs.device)
     with torch.cuda.device(coeffs.device):
         rc = lib().pr_backward(_ptr(coeffs), _ptr(degrees), _ptr(roots), _ptr(grad_roots), n, dmax,
                                _ptr(grad_coeffs), _ptr(status), _stream(stream))
@@ -283,7 +286,7 @@ def l2fit(samples, degree: int, nr: int, nt: int, coeffs=None, stream=None):
     n = samples.shape[1]
     if coeffs is None:
         coeffs = torch.empty((degree + 1, n), dtype=torch.complex128, device=samples.device)
-    _check(coeffs, "coeffs", torch.complex128, (degree + 1, n))
+    _check(coeffs, "coeffs", torch.complex128, (degree + 1, n), device=samples.device)
     with torch.cuda.device(samples.device):
         rc = lib().pr_l2fit(_ptr(samples), n, degree, nr, nt, _ptr(coeffs), _stream(stream))
     if rc != PR_OK:
@@ -297,17 +300,17 @@ def density_local(roots, centers, radii, window, shape, rmax2=1.0, degrees=None,
     i counts iff |w|^2 < rmax2, at z = centers[i] + radii[i] * w."""
     _check(roots, "roots", torch.complex128)
     dmax, n = roots.shape
-    _check(centers, "centers", torch.complex128, (n,))
-    _check(radii, "radii", torch.float64, (n,))
+    _check(centers, "centers", torch.complex128, (n,), device=roots.device)
+    _check(radii, "radii", torch.float64, (n,), device=roots.device)
     x0, x1, y0, y1 = (float(v) for v in window)
     width, height = (int(v) for v in shape)
     if out is None:
         out = torch.zeros((height, width), dtype=torch.int32, device=roots.device)
-    _check(out, "out", torch.int32, (height, width))
+    _check(out, "out", torch.int32, (height, width), device=roots.device)
     if degrees is not None:
-        _check(degrees, "degrees", torch.int32, (n,))
+        _check(degrees, "degrees", torch.int32, (n,), device=roots.device)
     if status is not None:
-        _check(status, "status", torch.int32, (n,))
+        _check(status, "status", torch.int32, (n,), device=roots.device)
     with torch.cuda.device(roots.device):
         rc = lib().pr_density_local(_ptr(roots), _ptr(degrees), _ptr(status), skip_mask & 0xFFFFFFFF,
                                     n, dmax, _ptr(centers), _ptr(radii), float(rmax2), x0, x1, y0,
