@@ -101,7 +101,11 @@ enum pr_solve_flags {
                                                shift per step as well, with fewer steps per
                                                level (a 2 x 2 block deflates in one); where
                                                its value is not finite (FP32 entries beyond
-                                               about 2^31) a step takes the bottom entry */
+                                               about 2^31) a step takes the bottom entry.
+                                               The default also shifts each polynomial's
+                                               first step by the root nearest 0 of
+                                               b_0 + b_1 z + b_2 z^2 (b monic), where both
+                                               rules would start from 0 */
 };
 
 /* Options of pr_solve.  Zero-initialised = defaults. */
