@@ -3,6 +3,7 @@
 // allocates, synchronises or throws.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 
 #include "internal.hpp"
@@ -21,21 +22,23 @@ constexpr int kMaxDevices = 64;
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? PR_OK : PR_ERR_HIP; }
 
-// Compute-unit count of the current device, looked up once per device.
+// Compute-unit count of the current device, looked up once per device (calls
+// from several host threads may look it up together; they store the same
+// value).
 int cu_count()
 {
-    static int cached[kMaxDevices] = {0};
+    static std::atomic<int> cached[kMaxDevices];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
         return 256;
-    if (cached[dev] == 0) {
-        int cus = 0;
+    int cus = cached[dev].load(std::memory_order_relaxed);
+    if (cus == 0) {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
-        cached[dev] = cus;
+        cached[dev].store(cus, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return cus;
 }
 
 }  // namespace
