@@ -191,8 +191,9 @@ def _median_ms(torch, fn, reps=15, warm=5):
 def bench_configs(args, torch, workloads, pr, dev):
     """The other workload configurations (medians of warm repeats, inputs
     resident in HBM): Gaussian 65,536 (eager and captured graph), known
-    roots 4 Mi (forward and backward), clustered 16 Mi (both forms), and
-    the FP64 fallback on known roots and clusters.  One JSON line."""
+    roots 4 Mi (forward and backward), clustered 16 Mi (both forms), the
+    FP64 fallback on known roots and clusters, and 16 Mi Gaussian
+    polynomials whose spread roots bin at the atomics' rate.  One JSON line."""
     import numpy as np
     from paper_2507_02164_amd.graph import PathGraph
     out = {}
@@ -254,6 +255,25 @@ def bench_configs(args, torch, workloads, pr, dev):
         out[f"clustered16M_{form}_flagged"] = flagged(s)
     out["clustered16M_fp32_polish_fallback_solve_ms"] = _median_ms(torch, lambda: pr.solve(
         a, None, "fp32_polish", roots=r, status=s, flags=pr.FLAG_FP64_FALLBACK), reps=5, warm=1)
+    del a, r, s, h
+
+    # spread roots: 16 Mi Gaussian degree-6 polynomials binned into a 1920x1080
+    # image over [-3, 3)^2, where neighbouring roots rarely share a pixel
+    log("gaussian 16 Mi, spread roots, 1920x1080 image")
+    a = torch.from_numpy(workloads.gaussian(16 * 2 ** 20, 0)).to(dev)
+    n = a.shape[1]
+    r = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    s = torch.empty((n,), dtype=torch.int32, device=dev)
+    win, shape = workloads.GAUSSIAN_WINDOW, (1920, 1080)
+    h = torch.zeros((1080, 1920), dtype=torch.int32, device=dev)
+    for form in ("fp32_polish", "fp64"):
+        out[f"gaussian16M_{form}_solve_ms"] = _median_ms(
+            torch, lambda: pr.solve(a, None, form, roots=r, status=s), reps=7, warm=2)
+        out[f"gaussian16M_{form}_solve_bin_ms"] = _median_ms(torch, lambda: (
+            h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r, status=s, out=h)),
+            reps=7, warm=2)
+    out["gaussian16M_density_ms"] = _median_ms(
+        torch, lambda: (h.zero_(), pr.density(r, win, shape, status=s, out=h)), reps=7, warm=2)
     print(json.dumps({"workload": "other configurations", "results": out}))
 
 
