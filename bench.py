@@ -277,6 +277,24 @@ def bench_configs(args, torch, workloads, pr, dev):
     print(json.dumps({"workload": "other configurations", "results": out}))
 
 
+def bench_hbm(torch, dev, gib=4):
+    """Bandwidth of plain torch kernels over a 4 GiB float64 array: a copy
+    (read + write), a sum (read), a fill (write); medians of 10.  The ceiling
+    the library's HBM-bound kernels (backward, L2 fit) are compared with."""
+    n = gib * 2 ** 30 // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    nb = n * 8
+
+    def tbps(nbytes, fn):
+        return nbytes / (_median_ms(torch, fn, reps=10, warm=1) * 1e-3) / 1e12
+
+    out = {"copy_TBps": tbps(2 * nb, lambda: dst.copy_(src)),
+           "read_sum_TBps": tbps(nb, lambda: src.sum()),
+           "write_fill_TBps": tbps(nb, lambda: dst.fill_(2.0))}
+    print(json.dumps({"workload": f"plain torch kernels over {gib} GiB", "results": out}))
+
+
 def bench_l2fit(args, torch, pr, dev, n=1 << 21, degree=6, nr=8, nt=16):
     """Sec. II-A front-end on its own: degree-6 least-squares fits of
     f(z) = sin z on 2^21 disks from 8 x 16 polar samples each.  HBM-bound:
@@ -317,10 +335,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--grid", type=int, default=4096, help="grid side; n = grid^2")
-    ap.add_argument("--workload", choices=["parametric", "mixed", "configs"], default="parametric",
+    ap.add_argument("--workload", choices=["parametric", "mixed", "configs", "hbm"],
+                    default="parametric",
                     help="parametric: the default timed workload; mixed: 64M polynomials of "
                          "degrees 2..6 (solve only, both launch layouts); configs: the other "
-                         "workload configurations and the FP64 fallback")
+                         "workload configurations and the FP64 fallback; hbm: the bandwidth "
+                         "plain torch kernels reach on this GPU (context for the HBM-bound "
+                         "kernels)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", choices=["fp32_polish", "fp64"], default=None,
                     help="run only the timed steps of one form (for profilers)")
@@ -352,6 +373,8 @@ def main():
         return bench_mixed(args, torch, workloads, pr, dev)
     if args.workload == "configs":
         return bench_configs(args, torch, workloads, pr, dev)
+    if args.workload == "hbm":
+        return bench_hbm(torch, dev)
     g = args.grid
     n = g * g
     log(f"generating parametric grid {g}x{g} ({n} polynomials)")
