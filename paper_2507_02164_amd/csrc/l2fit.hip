@@ -25,6 +25,7 @@ namespace proots {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kBatch = 8;
 
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void l2fit_kernel(const double2* __restrict__ samples,
@@ -44,7 +45,26 @@ __global__ __launch_bounds__(kBlock) void l2fit_kernel(const double2* __restrict
         acc[j] = {0.0, 0.0};
     for (int ir = 0; ir < qd.nr; ++ir) {
         const double r = qd.r[ir], om = qd.w[ir];
-        for (int it = 0; it < qd.nt; ++it) {
+        int it = 0;
+        // the samples of kBatch angles are loaded before any is used, so a
+        // wave keeps kBatch loads in flight instead of one
+        for (; it + kBatch <= qd.nt; it += kBatch) {
+            double2 f[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b)
+                f[b] = samples[(int64_t)(ir * qd.nt + it + b) * n + i];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const cx<double> cw = {r * cs[it + b], -r * sn[it + b]};  // conj(w_q)
+                cx<double> t = {f[b].x * om, f[b].y * om};
+#pragma unroll
+                for (int j = 0; j <= DEG; ++j) {
+                    acc[j] = acc[j] + t;
+                    t = t * cw;
+                }
+            }
+        }
+        for (; it < qd.nt; ++it) {
             const double2 f = samples[(int64_t)(ir * qd.nt + it) * n + i];
             const cx<double> cw = {r * cs[it], -r * sn[it]};  // conj(w_q)
             cx<double> t = {f.x * om, f.y * om};
