@@ -112,12 +112,30 @@ def cpu_baseline(coeffs_host, target_s=10.0):
     t0 = time.perf_counter()
     roots, st = oracle.solve(sample, flags=flags)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over a sample of about target_s / 4
+    n1 = int(min(n_total, max(4096, rate / max(threads, 1) * target_s / 4)))
+    t0 = time.perf_counter()
+    oracle.solve(np.ascontiguousarray(coeffs_host[:, :n1]), flags=flags, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {
         "value": n / dt, "unit": "polys/s", "cores": threads, "kind": "oracle",
         "sample": f"first {n} polynomials of the same grid (rows 0..{(n - 1) // 4096} of 4096), "
                   f"FP64 oracle solve only, shift rule as on the GPU, {dt:.1f} s",
-        "host_cpu": platform.processor() or platform.machine(),
+        "single_thread": {"value": n1 / dt1, "unit": "polys/s", "cores": 1,
+                          "sample": f"first {n1} polynomials of the same grid, {dt1:.1f} s"},
+        "host_cpu": _cpu_model(), "nproc": os.cpu_count(),
     }, roots, n
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def bench_mixed(args, torch, workloads, pr, dev):

@@ -54,3 +54,14 @@ def test_traffic_record_only_for_the_profiled_kernel_and_workload():
     # either the record matches the built kernel (a plausible byte count) or
     # the kernel changed since it was taken / nothing is built (None)
     assert t is None or 3e9 < t < 2e10
+
+
+def test_cpu_baseline_reports_all_cores_and_one_thread():
+    import workloads
+    a = workloads.gaussian(20000, seed=3)
+    r, roots, n = bench.cpu_baseline(a, target_s=0.2)
+    assert r["kind"] == "oracle" and r["unit"] == "polys/s" and r["value"] > 0
+    assert roots.shape == (6, n) and 0 < n <= a.shape[1]
+    one = r["single_thread"]
+    assert one["cores"] == 1 and one["value"] > 0
+    assert r["nproc"] >= 1 and r["host_cpu"]
