@@ -30,6 +30,27 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
     if (i >= n)
         return;
     const int d = degrees ? degrees[i] : DM;
+    // the rows are loaded before the status word is looked at, so that no
+    // load waits on another; rows k <= min(d, DM) are in bounds for any d
+    cx<double> a[DM + 1], r[DM], gr[DM];
+#pragma unroll
+    for (int k = 0; k <= DM; ++k) {
+        a[k] = {0.0, 0.0};
+        if (d >= 1 && k <= d) {
+            const double2 v = load_stream(coeffs + (int64_t)k * n + i);
+            a[k] = {v.x, v.y};
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        r[j] = gr[j] = {0.0, 0.0};
+        if (j < d) {
+            const double2 rv = load_stream(roots + (int64_t)j * n + i);
+            const double2 gv = load_stream(grad_roots + (int64_t)j * n + i);
+            r[j] = {rv.x, rv.y};
+            gr[j] = {gv.x, gv.y};
+        }
+    }
     uint32_t st = status[i];
     cx<double> g[DM + 1];
 #pragma unroll
@@ -38,26 +59,6 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
     const bool valid = d >= 1 && d <= DM &&
                        !(st & (PR_ST_BAD_DEGREE | PR_ST_NONFINITE | PR_ST_ZERO_LEADING));
     if (valid) {
-        // every load first (all rows in flight together), then the arithmetic
-        cx<double> a[DM + 1], r[DM], gr[DM];
-#pragma unroll
-        for (int k = 0; k <= DM; ++k) {
-            a[k] = {0.0, 0.0};
-            if (k <= d) {
-                double2 v = coeffs[(int64_t)k * n + i];
-                a[k] = {v.x, v.y};
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < DM; ++j) {
-            r[j] = gr[j] = {0.0, 0.0};
-            if (j < d) {
-                const double2 rv = roots[(int64_t)j * n + i];
-                const double2 gv = grad_roots[(int64_t)j * n + i];
-                r[j] = {rv.x, rv.y};
-                gr[j] = {gv.x, gv.y};
-            }
-        }
 #pragma unroll
         for (int j = 0; j < DM; ++j) {
             if (j < d) {
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void backward_kernel(
     }
 #pragma unroll
     for (int k = 0; k <= DM; ++k)
-        grad_coeffs[(int64_t)k * n + i] = make_double2(g[k].re, g[k].im);
+        store_stream(grad_coeffs + (int64_t)k * n + i, make_double2(g[k].re, g[k].im));
     status[i] = st;
 }
 

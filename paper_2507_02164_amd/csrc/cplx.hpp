@@ -59,4 +59,20 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b)
     return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
 }
 
+// Read-once and write-once streams (a kernel's inputs and outputs that no
+// later access of the same launch reuses): nontemporal accesses, which keep
+// them from displacing reusable lines in the caches.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 load_stream(const double2* p)
+{
+    const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2*>(p));
+    return make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ void store_stream(double2* p, double2 v)
+{
+    __builtin_nontemporal_store(nt_double2{v.x, v.y}, reinterpret_cast<nt_double2*>(p));
+}
+
 }  // namespace proots

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void l2fit_kernel(const double2* __restrict
             double2 f[kBatch];
 #pragma unroll
             for (int b = 0; b < kBatch; ++b)
-                f[b] = samples[(int64_t)(ir * qd.nt + it + b) * n + i];
+                f[b] = load_stream(samples + (int64_t)(ir * qd.nt + it + b) * n + i);
 #pragma unroll
             for (int b = 0; b < kBatch; ++b) {
                 const cx<double> cw = {r * cs[it + b], -r * sn[it + b]};  // conj(w_q)
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void l2fit_kernel(const double2* __restrict
             }
         }
         for (; it < qd.nt; ++it) {
-            const double2 f = samples[(int64_t)(ir * qd.nt + it) * n + i];
+            const double2 f = load_stream(samples + (int64_t)(ir * qd.nt + it) * n + i);
             const cx<double> cw = {r * cs[it], -r * sn[it]};  // conj(w_q)
             cx<double> t = {f.x * om, f.y * om};
 #pragma unroll
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void l2fit_kernel(const double2* __restrict
 #pragma unroll
     for (int j = 0; j <= DEG; ++j) {
         const double s = (j + 1) / M_PI;
-        coeffs[(int64_t)j * n + i] = make_double2(acc[j].re * s, acc[j].im * s);
+        store_stream(coeffs + (int64_t)j * n + i, make_double2(acc[j].re * s, acc[j].im * s));
     }
 }
 

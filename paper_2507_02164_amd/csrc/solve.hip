@@ -721,7 +721,7 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
                 if (k <= d) {
                     // a_k 2^(s (k - d)): the coefficients of 2^(-s d) p(2^s w),
                     // so that the polish below runs in the sweeps' variable w
-                    const double2 v = io.coeffs_again[(int64_t)k * n + i];
+                    const double2 v = load_stream(io.coeffs_again + (int64_t)k * n + i);
                     const int e = sc * (k - d);
                     a[k] = {__builtin_ldexp(v.x, e), __builtin_ldexp(v.y, e)};
                 }
@@ -763,7 +763,7 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
             for (int k = 0; k < DM; ++k)
                 if (k < d) {
                     if (store)
-                        io.roots[(int64_t)k * n + i] = make_double2(r[k].re, r[k].im);
+                        store_stream(io.roots + (int64_t)k * n + i, make_double2(r[k].re, r[k].im));
                     if constexpr (BIN != kBinNone)
                         bins[k] = pixel_of(r[k].re, r[k].im, io.win);
                 }
