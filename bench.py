@@ -606,7 +606,11 @@ def main():
             mm = np.take_along_axis(rr, best, axis=0)
             e = np.abs(mm - ref) / np.abs(ref)
             ok = ss == 0
-            errs[form] = {"max_rel_err_unflagged": float(e[:, ok].max()),
+            eu = e[:, ok].ravel()
+            errs[form] = {"max_rel_err_unflagged": float(eu.max()) if eu.size else None,
+                          "rel_err_percentiles_unflagged": {
+                              f"p{q:g}": float(np.percentile(eu, q)) for q in (50, 90, 99, 99.9)}
+                          if eu.size else None,
                           "flagged": int((~ok).sum()), "checked_polys": int(sel.size)}
         out["accuracy_vs_oracle"] = errs
     print(json.dumps(out))
