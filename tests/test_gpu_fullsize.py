@@ -44,7 +44,12 @@ def test_parametric_full_both_forms_and_image():
     _say("oracle on all 16.7M polynomials")
     ref, ref_st = oracle.solve(a, flags=OW)
     idx = _sample(n, 8192)
+    tidx = torch.from_numpy(idx)
     kappa = rel_condition(a[:, idx], ref[:, idx])
+    win, shape = workloads.PARAMETRIC_WINDOW, (1920, 1080)
+    want_img = oracle.density(ref, win, shape)
+    cot = workloads.cotangents(n, seed=1)
+    ccot = to_dev(cot)
     for form in ("fp32_polish", "fp64"):
         r, st = pr.solve(ca, None, form)
         torch.cuda.synchronize()
@@ -52,18 +57,44 @@ def test_parametric_full_both_forms_and_image():
         assert (st_h & ~pr.ST_POLISH_UNCONVERGED).max() == 0
         flagged = (st_h != 0)
         assert flagged.mean() < 1e-4, (form, flagged.mean())
-        rs = to_host(r[:, torch.from_numpy(idx).to(r.device)])
+        rs = to_host(r[:, tidx.to(r.device)])
         ok = ~flagged[idx]
         err = rel_err(match(rs, ref[:, idx]), ref[:, idx])
         assert np.all(err[:, ok] <= parity_bound(kappa[:, ok])), form
         _say(f"{form}: max rel err {err[:, ok].max():.2e} on {ok.sum()} sampled polys, "
              f"{flagged.sum()} flagged of {n}")
-        del r, st
+
+        # the benchmark's step: solve + bin in one launch into caller arrays,
+        # then the backward on the grid's cotangents
+        r2 = torch.empty_like(r)
+        s2 = torch.empty_like(st)
+        img = torch.zeros((shape[1], shape[0]), dtype=torch.int32, device=r.device)
+        pr.solve_bin(ca, win, shape, None, form, roots=r2, status=s2, out=img)
+        gc = torch.empty_like(ca)
+        pr.backward(ca, r2, ccot, None, s2, grad_coeffs=gc)
+        torch.cuda.synchronize()
+        # one launch gives the same roots, bit for bit, as pr_solve
+        assert torch.equal(torch.view_as_real(r2).view(torch.int64),
+                           torch.view_as_real(r).view(torch.int64)), form
+        img_h = to_host(img)
+        assert np.array_equal(img_h, to_host(pr.density(r2, win, shape))), form
+        # against the oracle's image only roots within rounding of a pixel
+        # edge (or flagged ones) may land elsewhere
+        moved = int(np.abs(img_h.astype(np.int64) - want_img).sum())
+        assert moved <= 12 * int(flagged.sum()) + 20, (form, moved)
+        # the backward on the benchmark's roots against the oracle's adjoint
+        want_g, want_gst = oracle.backward(a[:, idx], to_host(r2[:, tidx.to(r2.device)]),
+                                           cot[:, idx], status=st_h[idx])
+        got_g = to_host(gc[:, tidx.to(gc.device)])
+        gerr = np.abs(got_g - want_g).max(axis=0) / np.abs(want_g).max(axis=0)
+        assert gerr[ok].max() < 1e-10, (form, gerr[ok].max())
+        assert np.array_equal(to_host(s2)[idx], want_gst.astype(to_host(s2).dtype)), form
+        _say(f"{form}: solve_bin + backward as benchmarked: image moved {moved}, "
+             f"gradient max rel diff {gerr[ok].max():.2e}")
+        del r, st, r2, s2, img, gc
     # the image binned on the GPU from the oracle's full root array is bit-exact
-    win, shape = workloads.PARAMETRIC_WINDOW, (1920, 1080)
-    want = oracle.density(ref, win, shape)
     got = to_host(pr.density(to_dev(ref), win, shape))
-    assert np.array_equal(got, want)
+    assert np.array_equal(got, want_img)
 
 
 def test_mixed_full_fp32_polish():
