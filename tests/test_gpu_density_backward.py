@@ -174,3 +174,27 @@ def test_gradcheck_tiny():
         return pr.roots(x)
 
     assert torch.autograd.gradcheck(f, (c,), eps=1e-7, atol=1e-6, rtol=1e-5)
+
+
+@pytest.mark.parametrize("n", [0, 1, 127, 128, 129, 1000])
+def test_backward_bad_degrees_and_ragged_sizes(n):
+    # degrees outside 1..dmax leave the gradient zero and the status as it
+    # was, whatever rows the coefficient array holds for them
+    rng = np.random.default_rng(11 + n)
+    a = workloads.gaussian(max(n, 1), seed=5)[:, :n]
+    ref, st = oracle.solve(a) if n else (np.zeros((6, 0), np.complex128), np.zeros(0, np.uint32))
+    deg = np.full(n, 6, dtype=np.int32)
+    bad = rng.random(n) < 0.3
+    deg[bad] = rng.choice(np.array([-3, 0, 7, 100], dtype=np.int32), size=int(bad.sum()))
+    g = workloads.cotangents(max(n, 1), seed=6)[:, :n]
+    r = np.nan_to_num(ref)
+    got, gst = pr.backward(to_dev(a), to_dev(r), to_dev(g), to_dev(deg),
+                           to_dev(st.astype(np.int32)))
+    want, wst = oracle.backward(a, r, g, deg, st)
+    got = to_host(got)
+    assert got.shape == (7, n)
+    assert np.all(got[:, bad] == 0) and np.all(want[:, bad] == 0)
+    assert np.array_equal(to_host(gst).astype(np.uint32), wst)
+    if (~bad).any():
+        scale = np.abs(want[:, ~bad]).max(axis=0)
+        assert (np.abs(got[:, ~bad] - want[:, ~bad]).max(axis=0) / scale).max() < 1e-10
