@@ -714,7 +714,11 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
         if (ok) {
             // The original coefficients, read again (through a second
             // pointer, so the compiler cannot keep the first load alive
-            // across the QR loop).
+            // across the QR loop).  This is their last use, so the read is
+            // nontemporal; the first read is an ordinary one so that they
+            // may still be in L2 here.  The roots are stored nontemporally
+            // below for the same reason: as ordinary stores they would evict
+            // coefficients that other waves are about to read again.
 #pragma unroll
             for (int k = 0; k <= DM; ++k) {
                 a[k] = {0.0, 0.0};
