@@ -49,8 +49,13 @@ def sources():
 
 def isa_digests(asm_text: str) -> dict:
     """{kernel symbol: SHA-256 of its instruction lines} for every kernel in
-    an AMDGPU assembly listing (comments, labels and directives dropped)."""
+    an AMDGPU assembly listing (comments, labels and directives dropped).
+    Branch targets name basic blocks as .LBB<function>_<block>; the function
+    number depends on how many functions precede the kernel in the file, so
+    it is dropped and an unchanged kernel keeps its digest."""
     import hashlib
+    import re
+    block = re.compile(r"\.LBB\d+_")
     out = {}
     name, body = None, []
     for line in asm_text.split("\n"):
@@ -58,7 +63,7 @@ def isa_digests(asm_text: str) -> dict:
             if line.startswith("_Z") and line.split(";")[0].rstrip().endswith(":"):
                 name, body = line.split(":")[0], []
             continue
-        ins = line.split(";")[0].strip()
+        ins = block.sub(".LBB_", line.split(";")[0].strip())
         if ins and not ins.startswith(".") and not ins.endswith(":"):
             body.append(ins)
         if ins.startswith("s_endpgm"):

@@ -49,13 +49,15 @@
 //     the status is final, the wave counts every lane's roots with merged
 //     atomics -- the same decisions and counts as the density kernel over
 //     the stored roots, without a second launch.  The FP32 form bins its
-//     polished roots from registers.  The FP64 form stores each root as it
-//     deflates; it either reads them back at the end (kBinReread: a few
-//     bytes more traffic, no extra registers across the QR loops) or, when
-//     the roots are not stored, keeps one pixel index per deflated root in
-//     registers (kBinKeep).  The matrix's diagonal cannot stand in for the
-//     deflated roots: the identity steps of lanes that ride along preserve
-//     values, not the sign of zeros or entries next to an overflowed one.
+//     polished roots from registers.  The FP64 form keeps one pixel index
+//     per deflated root in registers (kBinKeep: 6 more VGPRs, still 3 waves
+//     per SIMD, and about 1% faster than reading stored roots back).  Only
+//     the FP64 fallback launch, which re-solves a sparse subset, stores its
+//     roots as they deflate and reads them back at the end (kBinReread: no
+//     extra registers across the QR loops).  The matrix's diagonal cannot
+//     stand in for the deflated roots: the identity steps of lanes that ride
+//     along preserve values, not the sign of zeros or entries next to an
+//     overflowed one.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -912,8 +914,6 @@ hipError_t launch_dm(const SolveArgs& a, hipStream_t stream)
     hipError_t e;
     if (!a.win.hist)
         e = launch_layout<FP32, DM, kBinNone>(io, a, stream);
-    else if (!FP32 && a.roots)
-        e = launch_layout<FP32, DM, FP32 ? kBinKeep : kBinReread>(io, a, stream);
     else
         e = launch_layout<FP32, DM, kBinKeep>(io, a, stream);
     if (e != hipSuccess || !fallback)
