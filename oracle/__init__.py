@@ -10,8 +10,9 @@ use when the shared library is missing, and wraps it for numpy arrays.
 
 What each function follows in arXiv 2507.02164:
   solve     -- Sec. II-B (companion matrix, Alg. 1 single-shift QR iteration)
-               and Sec. II-C (Givens equation, two-row then two-column
-               in-place update, the loop shape of Alg. 2), with a
+               and Sec. II-C (the Givens rotations whose product gives each
+               step's QR factorisation; the step itself is formed with dense
+               matrix products), with a
                convergence test and exceptional shift where the paper has a
                fixed iteration count (``fixed_t`` reproduces Alg. 2), and,
                with ``FLAG_WILKINSON_SHIFT``, Wilkinson's shift (the
@@ -250,8 +251,9 @@ def quadratic_start(b0: complex, b1: complex, b2: complex):
 
 
 def qr_step(H, shift: complex):
-    """One shifted QR step (Alg. 1 body via Sec. II-C rotations) on a dense
-    square complex matrix; returns the new matrix."""
+    """One shifted QR step (Alg. 1 body: A - sI = QR with Q from the Sec.
+    II-C rotations, A <- RQ + sI by dense products) on a dense square
+    complex matrix; returns the new matrix."""
     H = np.array(H, dtype=np.complex128, copy=True, order="C")
     m = H.shape[0]
     assert H.shape == (m, m) and 1 <= m <= 6

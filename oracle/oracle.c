@@ -11,19 +11,21 @@
  * What it computes:
  *   oracle_solve     -- roots of p(z) = sum_k a_k z^k as eigenvalues of the
  *                       Frobenius companion matrix (Sec. II-B), by
- *                       single-shift QR iteration (Alg. 1) whose QR step is
- *                       realised with complex Givens rotations applied to two
- *                       rows, then two columns, in place (Sec. II-C, the loop
- *                       structure of Alg. 2), with bottom deflation.
+ *                       single-shift QR iteration (Alg. 1) with bottom
+ *                       deflation; each step's factorisation A - sI = QR is
+ *                       built from the complex Givens rotations of Sec. II-C,
+ *                       and the step A <- RQ + sI is formed with dense matrix
+ *                       products.
  *   oracle_density   -- roots -> integer pixel counts over a complex window
  *                       (Sec. III, the roots-to-pixels stage).
  *   oracle_backward  -- implicit-function adjoint dr/da_k = -r^k / p'(r).
  *                       The paper has no gradient; this is the textbook
  *                       derivative of a simple root, written out.
  *
- * Storage is a dense row-major d x d matrix and every loop runs over the
- * dense range Alg. 2 gives (j = 0..m-1); there is no band trimming, fusion
- * or reordering.  Floating point: compiled with -O2 -ffp-contract=off, so
+ * Storage is a dense row-major d x d matrix; every rotation is formed as a
+ * full m x m matrix and applied by a dense matrix product, so there is no
+ * band trimming, fusion or in-place shortcut.  Floating point: compiled
+ * with -O2 -ffp-contract=off, so
  * every complex operation is a sequence of correctly rounded IEEE double
  * operations (gcc's C99 complex multiply/divide).
  *
@@ -39,7 +41,8 @@
  *     deflates once cabs1(h[m-1][m-2]) <= eps * (cabs1(h[m-1][m-1]) +
  *     cabs1(h[m-2][m-2])), cabs1(z) = |Re z| + |Im z|, eps = 2^-52;
  *   - exceptional shift at the 10th and 20th iteration of a level:
- *     s += cabs1(h[m-1][m-2]) * (0.75 + 0.5i); cap of 30 iterations per
+ *     s = h[m-1][m-1] + cabs1(h[m-1][m-2]) * (0.75 + 0.5i), whichever shift
+ *     rule is in force otherwise; cap of 30 iterations per
  *     level, after which the level deflates anyway and NOT_CONVERGED is set;
  *   - a fixed-T mode (flag) reproduces Alg. 2 literally: exactly T QR steps
  *     per level, no test, no exceptional shift;
@@ -107,44 +110,70 @@ void oracle_givens(const double *a_ri, const double *b_ri, double *c_ri, double 
     s_ri[1] = cimag(s);
 }
 
+/* Z = X Y for m x m matrices (row-major, leading dimension m): the plain
+ * dense product, each entry summed over k = 0..m-1 in order. */
+static void matmul(int m, const cplx *X, const cplx *Y, cplx *Z)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            cplx acc = 0.0;
+            for (int k = 0; k < m; ++k)
+                acc += X[i * m + k] * Y[k * m + j];
+            Z[i * m + j] = acc;
+        }
+}
+
 /* One shifted QR step on the leading m x m block of the dense matrix H
- * (row-major, leading dimension ld), Alg. 1 body: A <- A - sI; A = QR;
- * A <- RQ + sI.  The QR factorisation is never formed: as Sec. II-C and
- * Alg. 2 describe, the rotations Q_1..Q_{m-1} are applied to two rows at a
- * time (A <- Q_{m-1}..Q_1 A), then their conjugate transposes to two
- * columns at a time (A <- A Q_1^H .. Q_{m-1}^H). */
+ * (row-major, leading dimension ld), Alg. 1 body: A - sI = QR, then
+ * A <- RQ + sI.  The factorisation comes from the Sec. II-C rotations:
+ * G_r is the identity except for the 2 x 2 block [[c, s], [-conj(s),
+ * conj(c)]] on rows and columns r-1, r, with (c, s) chosen from the matrix
+ * G_{r-1}...G_1 (A - sI) reached so far so that its entry (r, r-1) becomes
+ * zero.  After r = 1..m-1 the product R = G (A - sI), G = G_{m-1}...G_1,
+ * is upper triangular and G is unitary, so A - sI = G^H R: Q = G^H and the
+ * new matrix is R G^H + sI.  Every product is a plain dense matrix product
+ * (matmul); the entry each rotation annihilates is then stored as an exact
+ * zero, which in exact arithmetic it is (Appendix). */
 static void qr_step(int m, int ld, cplx *H, cplx shift)
 {
-    cplx c[ODMAX], sn[ODMAX];
-#define E(i, j) H[(i) * ld + (j)]
+    cplx R[ODMAX * ODMAX], G[ODMAX * ODMAX], Gr[ODMAX * ODMAX], T[ODMAX * ODMAX];
     for (int i = 0; i < m; ++i)
-        E(i, i) -= shift;
-    /* row pass */
+        for (int j = 0; j < m; ++j) {
+            R[i * m + j] = H[i * ld + j];
+            G[i * m + j] = i == j ? 1.0 : 0.0;
+        }
+    for (int i = 0; i < m; ++i)
+        R[i * m + i] -= shift;
     for (int r = 1; r < m; ++r) {
-        double a[2] = {creal(E(r - 1, r - 1)), cimag(E(r - 1, r - 1))};
-        double b[2] = {creal(E(r, r - 1)), cimag(E(r, r - 1))};
+        double a[2] = {creal(R[(r - 1) * m + r - 1]), cimag(R[(r - 1) * m + r - 1])};
+        double b[2] = {creal(R[r * m + r - 1]), cimag(R[r * m + r - 1])};
         double cc[2], ss[2];
         oracle_givens(a, b, cc, ss);
-        c[r] = cc[0] + I * cc[1];
-        sn[r] = ss[0] + I * ss[1];
-        for (int j = 0; j < m; ++j) {
-            cplx x = E(r - 1, j), y = E(r, j);
-            E(r - 1, j) = c[r] * x + sn[r] * y;
-            E(r, j) = -conj(sn[r]) * x + conj(c[r]) * y;
-        }
-        E(r, r - 1) = 0.0; /* exact zero: the entry the rotation annihilates */
+        cplx c = cc[0] + I * cc[1], s = ss[0] + I * ss[1];
+        for (int k = 0; k < m * m; ++k)
+            Gr[k] = 0.0;
+        for (int i = 0; i < m; ++i)
+            Gr[i * m + i] = 1.0;
+        Gr[(r - 1) * m + (r - 1)] = c;
+        Gr[(r - 1) * m + r] = s;
+        Gr[r * m + (r - 1)] = -conj(s);
+        Gr[r * m + r] = conj(c);
+        matmul(m, Gr, R, T);
+        memcpy(R, T, sizeof(cplx) * m * m);
+        R[r * m + (r - 1)] = 0.0;
+        matmul(m, Gr, G, T);
+        memcpy(G, T, sizeof(cplx) * m * m);
     }
-    /* column pass */
-    for (int r = 1; r < m; ++r) {
-        for (int j = 0; j < m; ++j) {
-            cplx x = E(j, r - 1), y = E(j, r);
-            E(j, r - 1) = conj(c[r]) * x + conj(sn[r]) * y;
-            E(j, r) = -sn[r] * x + c[r] * y;
-        }
-    }
+    cplx GH[ODMAX * ODMAX];
     for (int i = 0; i < m; ++i)
-        E(i, i) += shift;
-#undef E
+        for (int j = 0; j < m; ++j)
+            GH[i * m + j] = conj(G[j * m + i]);
+    matmul(m, R, GH, T);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            H[i * ld + j] = T[i * m + j];
+    for (int i = 0; i < m; ++i)
+        H[i * ld + i] += shift;
 }
 
 /* Exposed for tests: one QR step with an explicit shift on a dense m x m
@@ -301,8 +330,11 @@ static unsigned solve_one(int d, const cplx *a, cplx *eig, int *its_out,
                 if (ok)
                     s = z;
             }
+            /* exceptional shift on the 10th and 20th step of a level: the
+             * bottom-right entry moved off by cabs1 of the subdiagonal entry,
+             * in place of whichever shift the rule would take */
             if (fixed_t <= 0 && !(flags & OFLAG_NO_EXCEPTIONAL_SHIFT) && (its == 10 || its == 20))
-                s += cabs1(hsub) * (0.75 + 0.5 * I);
+                s = H[(m - 1) * d + (m - 1)] + cabs1(hsub) * (0.75 + 0.5 * I);
             qr_step(m, d, H, s);
             ++its;
         }

@@ -146,3 +146,76 @@ def test_roots_of_c_with_the_shift(d, c):
         assert st[0] == 0 and its[0, 0] == 1
     else:
         assert st[0] & oracle.ST_NOT_CONVERGED
+
+
+def _cabs1(z):
+    return abs(z.real) + abs(z.imag)
+
+
+def _step_by_step(a, flags, cap=30):
+    """The level loop of Alg. 1 driven from Python through the oracle's
+    separately pinned pieces (one QR step, Wilkinson's shift, the quadratic
+    start), with the shift chosen as the readings state: the 10th and 20th
+    step of a level take the bottom-right entry plus cabs1(subdiagonal)
+    (0.75 + 0.5i) whatever the rule, the polynomial's first step the
+    quadratic start (when defined), every other step the rule's shift.
+    Monic degree-6 a [7].  Returns (roots in deflation order, steps per
+    level, number of exceptional steps where Wilkinson's shift differed
+    from the bottom entry)."""
+    d = 6
+    b = a[:d].astype(np.complex128)
+    H = np.zeros((d, d), dtype=np.complex128)
+    H[0, :] = -b[::-1]
+    for i in range(d - 1):
+        H[i + 1, i] = 1.0
+    eig = np.zeros(d, dtype=np.complex128)
+    its_all = np.zeros(d - 1, dtype=np.int32)
+    moved = 0
+    for m in range(d, 1, -1):
+        its = 0
+        while True:
+            hsub = H[m - 1, m - 2]
+            if _cabs1(hsub) <= 2.0 ** -52 * (_cabs1(H[m - 1, m - 1]) + _cabs1(H[m - 2, m - 2])):
+                break
+            if its == cap:
+                break
+            e = H[m - 1, m - 1]
+            s = e
+            if flags & W:
+                s = oracle.wilkinson_shift(H[m - 2, m - 2], H[m - 2, m - 1], hsub, e)
+            if (flags & oracle.FLAG_QUADRATIC_START) and m == d and its == 0:
+                z, ok = oracle.quadratic_start(b[0], b[1], b[2])
+                if ok:
+                    s = z
+            if its in (10, 20):
+                moved += int((flags & W) != 0 and s != e)
+                s = e + _cabs1(hsub) * (0.75 + 0.5j)
+            H[:m, :m] = oracle.qr_step(H[:m, :m], s)
+            its += 1
+        its_all[m - 2] = its
+        eig[m - 1] = H[m - 1, m - 1]
+    eig[0] = H[0, 0]
+    return eig, its_all, moved
+
+
+@pytest.mark.parametrize("flags", [0, W, W | oracle.FLAG_QUADRATIC_START])
+def test_exceptional_step_takes_the_bottom_entry_under_either_rule(flags):
+    """Reading R5: on the 10th and 20th step of a level the shift is the
+    bottom-right entry moved off by cabs1(h[m-1][m-2]) (0.75 + 0.5i), under
+    Alg. 1's shift and under Wilkinson's alike.  Triple root clusters take
+    such steps; the batched solve must follow the step-by-step driver bit
+    for bit, including polynomials where Wilkinson's shift at that step
+    differs from the bottom entry."""
+    coeffs, _ = workloads.clustered(3000, seed=5)
+    _, _, its = oracle.solve(coeffs, flags=flags, return_iters=True)
+    pick = np.nonzero(its.max(axis=0) >= 11)[0][:24]
+    assert pick.size >= 8, "too few polynomials reach an exceptional step"
+    roots, st, its = oracle.solve(coeffs[:, pick], flags=flags, return_iters=True)
+    moved = 0
+    for j, i in enumerate(pick):
+        eig, its_py, mv = _step_by_step(coeffs[:, i], flags)
+        moved += mv
+        np.testing.assert_array_equal(its[:, j], its_py)
+        np.testing.assert_array_equal(roots[:, j], eig)
+    if flags & W:
+        assert moved > 0
