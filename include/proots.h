@@ -25,8 +25,8 @@
  *     enqueues work on it and returns; nothing synchronises the device.
  *   - With n == 0 nothing is enqueued and the per-polynomial array pointers
  *     may be NULL.  A batch may hold up to (2^31 - 1) * 64 polynomials
- *     (pr_solve, pr_solve_bin) or about (2^31 - 1) * 256 (the other calls);
- *     a larger n is an argument error.
+ *     (pr_solve, pr_solve_bin), (2^31 - 1) * 128 (pr_backward) or about
+ *     (2^31 - 1) * 256 (the other calls); a larger n is an argument error.
  *   - The return value reports argument errors, detected on the host before
  *     anything is enqueued, and kernel-launch failures.  Numerical outcomes
  *     per polynomial are reported only through `status` bits, never as

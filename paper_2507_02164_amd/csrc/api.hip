@@ -162,7 +162,7 @@ static int density_common(const pr_complex* roots, const int32_t* degrees,
         return rc;
     if (n == 0)
         return PR_OK;
-    if (n > kMaxStreamBatch)
+    if (n > kMaxDensityBatch)
         return PR_ERR_INVALID_ARG;
     DensityArgs a;
     a.roots = roots;
@@ -227,7 +227,7 @@ extern "C" int pr_l2fit(const pr_complex* samples, int64_t n, int32_t degree, in
         return PR_ERR_INVALID_ARG;
     if (n == 0)
         return PR_OK;
-    if (n > kMaxStreamBatch)
+    if (n > kMaxL2fitBatch)
         return PR_ERR_INVALID_ARG;
     L2FitArgs a;
     a.samples = samples;
@@ -249,7 +249,7 @@ extern "C" int pr_backward(const pr_complex* coeffs, const int32_t* degrees,
         return PR_ERR_INVALID_ARG;
     if (n == 0)
         return PR_OK;
-    if (n > kMaxStreamBatch)
+    if (n > kMaxBackwardBatch)
         return PR_ERR_INVALID_ARG;
     BackwardArgs a;
     a.coeffs = coeffs;

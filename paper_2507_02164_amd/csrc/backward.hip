@@ -18,7 +18,7 @@
 namespace proots {
 namespace {
 
-constexpr int kBlock = 128;  // measured 2-4% faster than 64, 256, 512 or 1024
+constexpr int kBlock = kBackwardBlock;
 
 template <int DM>
 __global__ __launch_bounds__(kBlock) void backward_kernel(

@@ -25,7 +25,7 @@
 namespace proots {
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kDensityBlock;
 
 template <int DM, bool LOCAL>
 __global__ __launch_bounds__(kBlock) void density_kernel(

@@ -10,10 +10,17 @@
 
 namespace proots {
 
-// Largest batch a launch covers: a one-dimensional grid holds at most
-// 2^31 - 1 blocks (64-lane blocks for the solve kernels, 256 for the others).
-constexpr int64_t kMaxSolveBatch = (int64_t)0x7fffffff * 64;
-constexpr int64_t kMaxStreamBatch = (int64_t)0x7fffffff * 256 - 8 * 256;
+// Block sizes of the one-pass kernels, and the largest batch each launch
+// covers: a one-dimensional grid holds at most 2^31 - 1 blocks (the density
+// grid is rounded up to a multiple of 8 blocks, one share per XCD).
+constexpr int kDensityBlock = 256;
+constexpr int kBackwardBlock = 128;  // measured 2-4% faster than 64, 256, 512 or 1024
+constexpr int kL2fitBlock = 256;
+constexpr int64_t kMaxGridBlocks = 0x7fffffff;
+constexpr int64_t kMaxSolveBatch = kMaxGridBlocks * 64;  // one-wave blocks
+constexpr int64_t kMaxDensityBatch = (kMaxGridBlocks - 7) * kDensityBlock;
+constexpr int64_t kMaxBackwardBatch = kMaxGridBlocks * kBackwardBlock;
+constexpr int64_t kMaxL2fitBatch = kMaxGridBlocks * kL2fitBlock;
 
 struct SolveArgs {
     const pr_complex* coeffs;

@@ -24,7 +24,7 @@
 namespace proots {
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kL2fitBlock;
 constexpr int kBatch = 8;
 
 template <int DEG>

@@ -64,3 +64,53 @@ def valid_mask(dmax: int, degrees, n: int):
     if degrees is None:
         return np.ones((dmax, n), dtype=bool)
     return np.arange(dmax)[:, None] < np.asarray(degrees)[None, :]
+
+
+def match_nearest(test, ref, chunk: int = 1 << 19):
+    """Like ``match`` for large batches.  Per polynomial, each reference
+    root is paired with its nearest tested root; where these pairings form a
+    permutation, that permutation is used (each root's distance is then the
+    smallest any pairing could give it, so a bound that holds for all of
+    them proves the two sets agree root by root); the other polynomials go
+    through the brute-force ``match``.  Returns (reordered test, number of
+    polynomials that needed the brute force)."""
+    test = np.asarray(test)
+    ref = np.asarray(ref)
+    d, n = ref.shape
+    assert test.shape == (d, n)
+    if d == 1:
+        return test.copy(), 0
+    out = np.empty_like(test)
+    full = (1 << d) - 1
+    fallback = 0
+    for s in range(0, n, chunk):
+        t = test[:, s:s + chunk]
+        r = ref[:, s:s + chunk]
+        dist = np.abs(t[:, None, :] - r[None, :, :])               # [i_test, j_ref, c]
+        dist = np.where(np.isnan(dist), np.inf, dist)
+        near = np.argmin(dist, axis=0)                              # [j_ref, c]
+        mask = np.bitwise_or.reduce(np.left_shift(1, near), axis=0)
+        perm = mask == full
+        out[:, s:s + chunk] = np.take_along_axis(t, near, axis=0)
+        bad = np.nonzero(~perm)[0]
+        if bad.size:
+            fallback += bad.size
+            out[:, s + bad] = match(t[:, bad], r[:, bad])
+    return out, fallback
+
+
+def match_mixed_nearest(test, ref, degrees):
+    """``match_nearest`` for mixed degrees (rows k < degree compared; rows
+    beyond keep their values).  Returns (reordered test, fallback count)."""
+    out = np.array(test, copy=True)
+    degrees = np.asarray(degrees)
+    fallback = 0
+    for d in np.unique(degrees):
+        d = int(d)
+        if d < 1 or d > ref.shape[0]:
+            continue
+        cols = np.nonzero(degrees == d)[0]
+        m, fb = match_nearest(test[:d, cols], ref[:d, cols])
+        out[:d, cols] = m
+        fallback += fb
+    return out, fallback

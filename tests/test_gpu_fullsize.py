@@ -1,7 +1,10 @@
 """Full-size GPU parity: each workload at its stated size, in the launch
-configuration the benchmark times, checked against the oracle on sampled
-polynomials (and, for the density images, on the full root array the
-oracle computes).  Host-side generation takes up to ~40 s per case.
+configuration the benchmark times, checked against the oracle: every root
+of the parametric grid (16.7M polynomials, both forms) and of the
+known-root batch (4M, with its adjoint), every 64th polynomial plus every
+flagged one of the 64M mixed-degree batch, a sample of the clustered batch,
+and the density images on the full root arrays.  Host-side generation and
+the oracle take up to about a minute per case.
 """
 from __future__ import annotations
 
@@ -13,7 +16,8 @@ import pytest
 import oracle
 import workloads
 from gpuutil import parity_bound, rel_condition, to_dev, to_host
-from rootmatch import match, match_mixed, rel_err, valid_mask
+from rootmatch import (match, match_mixed_nearest, match_nearest, rel_err,
+                       valid_mask)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -36,6 +40,34 @@ def _sample(n, k, seed=0):
     return np.sort(rng.choice(n, size=min(k, n), replace=False))
 
 
+def _all_roots_within(got, ref, a, floor, skip=None, deg=None):
+    """Every root of every polynomial (columns with ``skip`` set excepted)
+    against the oracle's: a pairing in which each root is within
+    max(floor, 1e3 kappa u) relative of its own oracle root.  The condition
+    numbers are computed only for roots beyond the floor.  Returns (largest
+    relative error over the checked roots, polynomials that needed the
+    brute-force assignment)."""
+    if deg is None:
+        m, fb = match_nearest(got, ref)
+    else:
+        m, fb = match_mixed_nearest(got, ref, deg)
+    err = rel_err(m, ref)
+    valid = valid_mask(ref.shape[0], deg, ref.shape[1])
+    check = valid.copy()
+    if skip is not None:
+        check &= ~skip[None, :]
+    assert not np.isnan(err[check]).any(), "NaN root where the oracle has one"
+    cols = np.nonzero(((err > floor) & check).any(axis=0))[0]
+    if cols.size:
+        dsub = None if deg is None else deg[cols]
+        kappa = rel_condition(a[:, cols], ref[:, cols], dsub)
+        sub = err[:, cols]
+        bad = check[:, cols] & ~(sub <= parity_bound(kappa, floor))
+        assert not bad.any(), (f"{bad.sum()} roots out of bound, worst {sub[bad].max():.3e}, "
+                               f"polynomial {cols[np.nonzero(bad.any(axis=0))[0][0]]}")
+    return float(err[check].max()), fb
+
+
 def test_parametric_full_both_forms_and_image():
     g = 4096
     a = workloads.parametric(g, seed=0)
@@ -43,9 +75,9 @@ def test_parametric_full_both_forms_and_image():
     ca = to_dev(a)
     _say("oracle on all 16.7M polynomials")
     ref, ref_st = oracle.solve(a, flags=OW)
+    assert np.all(ref_st == 0)
     idx = _sample(n, 8192)
     tidx = torch.from_numpy(idx)
-    kappa = rel_condition(a[:, idx], ref[:, idx])
     win, shape = workloads.PARAMETRIC_WINDOW, (1920, 1080)
     want_img = oracle.density(ref, win, shape)
     cot = workloads.cotangents(n, seed=1)
@@ -57,12 +89,11 @@ def test_parametric_full_both_forms_and_image():
         assert (st_h & ~pr.ST_POLISH_UNCONVERGED).max() == 0
         flagged = (st_h != 0)
         assert flagged.mean() < 1e-4, (form, flagged.mean())
-        rs = to_host(r[:, tidx.to(r.device)])
+        # every root of all 16.7M polynomials against the oracle's
+        worst, fb = _all_roots_within(to_host(r), ref, a, 1e-10, skip=flagged)
         ok = ~flagged[idx]
-        err = rel_err(match(rs, ref[:, idx]), ref[:, idx])
-        assert np.all(err[:, ok] <= parity_bound(kappa[:, ok])), form
-        _say(f"{form}: max rel err {err[:, ok].max():.2e} on {ok.sum()} sampled polys, "
-             f"{flagged.sum()} flagged of {n}")
+        _say(f"{form}: max rel err {worst:.2e} over all {n} polynomials "
+             f"({fb} needed the brute-force pairing), {flagged.sum()} flagged")
 
         # the benchmark's step: solve + bin in one launch into caller arrays,
         # then the backward on the grid's cotangents
@@ -98,31 +129,38 @@ def test_parametric_full_both_forms_and_image():
 
 
 def test_mixed_full_fp32_polish():
+    """64 Mi mixed-degree polynomials through the autotuned persistent
+    launch: every 64th polynomial and every flagged one against the oracle.
+    The status bits the method decides (NOT_CONVERGED) agree with the
+    oracle's on all of them; every root of an unflagged polynomial is within
+    1e-8 relative (or its rounding floor); POLISH_UNCONVERGED, which the
+    oracle has no counterpart of, stays rare."""
     n = 64 * 2 ** 20
     _say("generating 64M mixed-degree polynomials")
     a, deg = workloads.mixed(n, seed=0)
     ca, cd = to_dev(a), to_dev(deg)
     r, st = pr.solve(ca, cd, "fp32_polish")
     torch.cuda.synchronize()
-    st_h = to_host(st)
+    st_h = to_host(st).astype(np.uint32)
     del ca
-    idx = _sample(n, 16384, seed=1)
-    flagged_all = (st_h & pr.ST_POLISH_UNCONVERGED) != 0
-    assert (st_h & (pr.ST_NOT_CONVERGED | 0x7)).max() == 0
-    assert flagged_all.mean() < 1e-2
-    # every flagged polynomial plus the sample are checked against the oracle
-    chk = np.union1d(idx, np.nonzero(flagged_all)[0][:4096])
+    assert (st_h & 0x7).max() == 0
+    flagged_all = (st_h & (pr.ST_NOT_CONVERGED | pr.ST_POLISH_UNCONVERGED)) != 0
+    assert flagged_all.mean() < 1e-5, flagged_all.mean()
+    chk = np.union1d(np.arange(0, n, 64), np.nonzero(flagged_all)[0])
+    _say(f"oracle on {chk.size} polynomials (every 64th and {flagged_all.sum()} flagged)")
     ref, ref_st = oracle.solve(a[:, chk], deg[chk], flags=OW)
+    nc_gpu = (st_h[chk] & pr.ST_NOT_CONVERGED) != 0
+    nc_ora = (ref_st & oracle.ST_NOT_CONVERGED) != 0
+    # a polynomial at the cap's edge may tip either way with the two sides'
+    # rounding; any more than a handful of disagreements would be a defect
+    disagree = int((nc_gpu != nc_ora).sum())
+    assert disagree <= max(2, chk.size // 100_000), (disagree, nc_gpu.sum(), nc_ora.sum())
     rs = to_host(r[:, torch.from_numpy(chk).to(r.device)])
-    m = match_mixed(rs, ref, deg[chk])
-    v = valid_mask(6, deg[chk], chk.size)
-    kappa = rel_condition(a[:, chk], ref, deg[chk])
-    err = rel_err(m, ref)
-    ok = ~flagged_all[chk]
-    bound = parity_bound(kappa, 1e-8)
-    assert np.all((err <= bound)[v & ok[None, :]])
-    _say(f"max rel err (unflagged) {err[v & ok[None, :]].max():.2e}; flagged {flagged_all.mean():.2e}; "
-         f"flagged polys' worst err {np.nanmax(np.where(v & ~ok[None, :], err, 0)):.2e}")
+    skip = flagged_all[chk] | nc_ora | nc_gpu
+    worst, fb = _all_roots_within(rs, ref, a[:, chk], 1e-8, skip=skip, deg=deg[chk])
+    _say(f"max rel err {worst:.2e} over {int((~skip).sum())} unflagged polynomials "
+         f"({fb} needed the brute-force pairing); flagged {flagged_all.sum()} of {n}, "
+         f"not converged on the oracle {nc_ora.sum()}")
 
 
 def test_known_roots_full_forward_and_backward():
@@ -133,11 +171,16 @@ def test_known_roots_full_forward_and_backward():
     r, st = pr.solve(c, None, "fp64")
     torch.cuda.synchronize()
     assert int((st != 0).sum()) == 0
-    idx = _sample(n, 8192, seed=2)
-    rs = to_host(r[:, torch.from_numpy(idx).to(r.device)])
-    kappa = rel_condition(coeffs[:, idx], roots_true[:, idx])
-    err = rel_err(match(rs, roots_true[:, idx]), roots_true[:, idx])
-    assert np.all(err <= np.maximum(1e-10, 64 * kappa * 2.0 ** -53))
+    # every root of all 4M polynomials against the generating roots (exact
+    # only up to the rounding of the expanded coefficients: a kappa-scaled
+    # bound where 1e-10 is out of reach)
+    m, fb = match_nearest(to_host(r), roots_true)
+    err = rel_err(m, roots_true)
+    cols = np.nonzero((err > 1e-10).any(axis=0))[0]
+    if cols.size:
+        kappa = rel_condition(coeffs[:, cols], roots_true[:, cols])
+        assert np.all(err[:, cols] <= np.maximum(1e-10, 64 * kappa * 2.0 ** -53))
+    _say(f"fp64 forward: max rel err vs the generating roots {err.max():.2e} over all {n}")
     # backward at full size on the oracle's roots; loss sum |r - t|^2 with
     # each root paired to its nearest generating root (gap >= 0.05)
     _say("oracle on all 4M polynomials")
@@ -147,11 +190,13 @@ def test_known_roots_full_forward_and_backward():
     grad_r = 2.0 * (ref - tgt)
     g, gst = pr.backward(c, to_dev(ref), to_dev(grad_r))
     torch.cuda.synchronize()
-    want, wst = oracle.backward(coeffs[:, idx], ref[:, idx], grad_r[:, idx])
-    got = to_host(g[:, torch.from_numpy(idx).to(g.device)])
+    # the adjoint of all 4M polynomials against the oracle's
+    want, wst = oracle.backward(coeffs, ref, grad_r)
+    got = to_host(g)
     gerr = np.abs(got - want).max(axis=0) / np.abs(want).max(axis=0)
     assert gerr.max() < 1e-10
-    assert int((gst != 0).sum()) == 0
+    assert int((gst != 0).sum()) == 0 and int((wst != 0).sum()) == 0
+    _say(f"backward: max rel diff {gerr.max():.2e} over all {n}")
 
 
 def test_clustered_full_classes_and_image():
