@@ -47,3 +47,26 @@ def parity_bound(kappa, floor=1e-10, c=1e3):
     rounding: max(floor, c * kappa * u).  Well-conditioned roots get the
     floor; for the rest the FP64 rounding floor itself scales with kappa."""
     return np.maximum(floor, c * kappa * U64)
+
+
+def deriv_condition(coeffs, roots, degrees=None):
+    """Condition number of evaluating p'(r_j) by any backward-stable sum:
+    sum_{k>=1} k |a_k| |r_j|^(k-1) / |p'(r_j)|, [dmax, n].  Two evaluations
+    with different rounding differ by up to about this times u relative, and
+    so do the adjoint terms -r^k / p'(r) built on them."""
+    dmax1, n = coeffs.shape
+    dmax = dmax1 - 1
+    deg = np.full(n, dmax) if degrees is None else np.asarray(degrees)
+    kk = np.arange(dmax1)[:, None]
+    a = np.where(kk <= deg[None, :], coeffs, 0)
+    out = np.full(roots.shape, np.inf)
+    for j in range(dmax):
+        r = roots[j]
+        pw = [np.ones(n, dtype=np.complex128)]
+        for k in range(dmax):
+            pw.append(pw[-1] * r)
+        num = sum(k * np.abs(a[k]) * np.abs(pw[k - 1]) for k in range(1, dmax1))
+        dp = sum(k * a[k] * pw[k - 1] for k in range(1, dmax1))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            out[j] = num / np.abs(dp)
+    return out

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import workloads
-from gpuutil import parity_bound, rel_condition, to_dev, to_host
+from gpuutil import deriv_condition, parity_bound, rel_condition, to_dev, to_host
 from rootmatch import (match, match_mixed_nearest, match_nearest, rel_err,
                        valid_mask)
 
@@ -194,9 +194,19 @@ def test_known_roots_full_forward_and_backward():
     want, wst = oracle.backward(coeffs, ref, grad_r)
     got = to_host(g)
     gerr = np.abs(got - want).max(axis=0) / np.abs(want).max(axis=0)
-    assert gerr.max() < 1e-10
+    # each adjoint term divides by p'(r_j); two evaluations of p' with
+    # different rounding differ by up to about its evaluation condition
+    # number times u, so the bound is max(1e-10, 1e3 kappa' u) per
+    # polynomial, kappa' the largest over its roots (the roots' own bound
+    # takes the same form)
+    kp = deriv_condition(coeffs, ref).max(axis=0)
+    bound = parity_bound(kp, 1e-10)
+    worst = int(np.argmax(gerr / bound))
+    assert np.all(gerr <= bound), (worst, gerr[worst], kp[worst])
     assert int((gst != 0).sum()) == 0 and int((wst != 0).sum()) == 0
-    _say(f"backward: max rel diff {gerr.max():.2e} over all {n}")
+    _say(f"backward: max rel diff {gerr.max():.2e} over all {n} "
+         f"({int((gerr > 1e-10).sum())} beyond 1e-10, kappa' up to {kp.max():.2e}); "
+         f"tightest: polynomial {worst}, {gerr[worst]:.2e} of {bound[worst]:.2e}")
 
 
 def test_clustered_full_classes_and_image():
