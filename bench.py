@@ -295,6 +295,141 @@ def bench_configs(args, torch, workloads, pr, dev):
     print(json.dumps({"workload": "other configurations", "results": out}))
 
 
+def mixed_flops(iters, deg, polish):
+    """Algorithmic FLOPs of a mixed-degree batch under the default shift
+    rule: steps x (F(m) + the shift's FLOPs) per level, the first shift
+    once per polynomial, and with ``polish`` the Newton steps of each
+    polynomial at its own degree.  iters [5, n] (row m-2 = level m)."""
+    fl = algorithmic_flops(iters)
+    if polish:
+        cnt = np.bincount(deg, minlength=7)
+        fl += float(sum(cnt[d] * polish_flops(d, 2) for d in range(1, 7)))
+    return fl
+
+
+def config_legs(args, torch, workloads, pr, dev):
+    """The other workload configurations, each at its stated size with
+    inputs resident in HBM: polys/s (median of warm repeats, HIP events on
+    the launch stream) and the fraction of the peak that bounds each call
+    under the algorithmic work model (VALU FP64 or FP32 from the measured
+    per-level step counts; HBM bytes for the backward)."""
+    out = {}
+    reps, warm = 7, 2
+
+    def flagged(st):
+        h = st.cpu().numpy().astype(np.uint32)
+        return {"not_converged": float(((h & pr.ST_NOT_CONVERGED) != 0).mean()),
+                "polish_unconverged": float(((h & pr.ST_POLISH_UNCONVERGED) != 0).mean())}
+
+    def leg(n, ms, flops, peak, **extra):
+        d = {"ms": ms, "polys_per_s": n / (ms * 1e-3),
+             "alg_tflops": flops / (ms * 1e-3) / 1e12, "peak_tflops": peak / 1e12,
+             "frac_of_peak": flops / (ms * 1e-3) / peak}
+        d.update(extra)
+        return d
+
+    # C1: 65,536 Gaussian degree-6 polynomials, FP64 (the configuration's
+    # form) and FP32 + polish, solve + 256 x 256 image in one launch
+    log("C1: gaussian 65,536, 256x256 image")
+    n = 65536
+    a = torch.from_numpy(workloads.gaussian(n, 0)).to(dev)
+    win, shape = workloads.GAUSSIAN_WINDOW, (256, 256)
+    h = torch.zeros((256, 256), dtype=torch.int32, device=dev)
+    r = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    s = torch.empty((n,), dtype=torch.int32, device=dev)
+    c1 = {"workload": "65,536 monic degree-6 Gaussian polynomials, 256x256 image over [-3,3)^2, "
+                      "image clear + pr_solve_bin"}
+    for form in ("fp64", "fp32_polish"):
+        _, st, its = pr.solve(a, None, form, iter_counts=True, roots=r, status=s)
+        fl = algorithmic_flops(its.cpu().numpy()) + (n * polish_flops(6, 2) if form != "fp64" else 0)
+        ms = _median_ms(torch, lambda: (h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r,
+                                                                 status=s, out=h)), reps, warm)
+        c1[form] = leg(n, ms, fl, PEAK_FP64 if form == "fp64" else PEAK_FP32, **flagged(s))
+    out["c1_gaussian65536"] = c1
+    del a, r, s, h
+
+    # C3: 64 Mi mixed-degree polynomials, one persistent autotuned launch,
+    # eager and replayed from a captured HIP graph
+    n = 64 * 2 ** 20
+    log("C3: generating 64Mi mixed-degree polynomials")
+    a_h, deg_h = workloads.mixed(n, 0)
+    a = torch.from_numpy(a_h).to(dev)
+    deg = torch.from_numpy(deg_h).to(dev)
+    del a_h
+    r = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    s = torch.empty((n,), dtype=torch.int32, device=dev)
+    c3 = {"workload": "64Mi polynomials, degrees uniform 2..6, moduli 10^U(-2,2), monic; "
+                      "pr_solve through the degree-sorted persistent launch (autotuned layout)"}
+    from paper_2507_02164_amd.graph import PathGraph
+    for form in ("fp32_polish", "fp64"):
+        log(f"C3: {form}")
+        _, _, its = pr.solve(a, deg, form, iter_counts=True, roots=r, status=s)
+        fl = mixed_flops(its.cpu().numpy(), deg_h, form != "fp64")
+        del its
+        peak = PEAK_FP64 if form == "fp64" else PEAK_FP32
+        ms = _median_ms(torch, lambda: pr.solve(a, deg, form, roots=r, status=s), reps, warm)
+        c3[form] = leg(n, ms, fl, peak, **flagged(s))
+        g = PathGraph(a, deg, form)
+        gms = _median_ms(torch, g.replay, reps, warm)
+        c3[form]["graph_replay"] = leg(n, gms, fl, peak, **flagged(g.status))
+        del g
+        torch.cuda.empty_cache()
+    out["c3_mixed64Mi"] = c3
+    del a, deg, r, s
+    torch.cuda.empty_cache()
+
+    # C4: 4 Mi known-root polynomials, FP64 forward + the adjoint
+    n = 4 * 2 ** 20
+    log("C4: known roots 4Mi")
+    coeffs = workloads.known_roots(n, 0)[0]
+    a = torch.from_numpy(coeffs).to(dev)
+    cot = torch.from_numpy(workloads.cotangents(n, 1)).to(dev)
+    r = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    s = torch.empty((n,), dtype=torch.int32, device=dev)
+    gc = torch.empty_like(a)
+    _, _, its = pr.solve(a, None, "fp64", iter_counts=True, roots=r, status=s)
+    fl = algorithmic_flops(its.cpu().numpy())
+    del its
+    fwd = _median_ms(torch, lambda: pr.solve(a, None, "fp64", roots=r, status=s), reps, warm)
+    bwd = _median_ms(torch, lambda: pr.backward(a, r, cot, None, s, grad_coeffs=gc), reps, warm)
+    both = _median_ms(torch, lambda: (pr.solve(a, None, "fp64", roots=r, status=s),
+                                      pr.backward(a, r, cot, None, s, grad_coeffs=gc)), reps, warm)
+    bbytes = 424 * n
+    out["c4_known_roots4Mi"] = {
+        "workload": "4Mi degree-6 polynomials from known roots (0.5<|z|<2, gap >= 0.05), FP64 "
+                    "pr_solve + pr_backward",
+        "forward_backward_ms": both, "polys_per_s": n / (both * 1e-3),
+        "forward": leg(n, fwd, fl, PEAK_FP64, **flagged(s)),
+        "backward": {"ms": bwd, "polys_per_s": n / (bwd * 1e-3), "alg_bytes": bbytes,
+                     "achieved_GBps": bbytes / (bwd * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": bbytes / (bwd * 1e-3) / PEAK_HBM}}
+    del a, cot, r, s, gc, coeffs
+
+    # C5: 16 Mi polynomials with a triple root cluster, both forms, solve +
+    # 1920 x 1080 image in one launch
+    n = 16 * 2 ** 20
+    log("C5: generating 16Mi clustered polynomials")
+    a = torch.from_numpy(workloads.clustered(n, 0)[0]).to(dev)
+    r = torch.empty((6, n), dtype=torch.complex128, device=dev)
+    s = torch.empty((n,), dtype=torch.int32, device=dev)
+    win, shape = workloads.CLUSTERED_WINDOW, (1920, 1080)
+    h = torch.zeros((1080, 1920), dtype=torch.int32, device=dev)
+    c5 = {"workload": "16Mi degree-6 polynomials, 3 roots within 1e-3 of a centre in the unit disk "
+                      "+ 3 in the unit disk; image clear + pr_solve_bin, 1920x1080"}
+    for form in ("fp32_polish", "fp64"):
+        log(f"C5: {form}")
+        _, _, its = pr.solve(a, None, form, iter_counts=True, roots=r, status=s)
+        fl = algorithmic_flops(its.cpu().numpy()) + (n * polish_flops(6, 2) if form != "fp64" else 0)
+        del its
+        ms = _median_ms(torch, lambda: (h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r,
+                                                                 status=s, out=h)), reps, warm)
+        c5[form] = leg(n, ms, fl, PEAK_FP64 if form == "fp64" else PEAK_FP32, **flagged(s))
+    out["c5_clustered16Mi"] = c5
+    del a, r, s, h
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_hbm(torch, dev, gib=4):
     """Bandwidth of plain torch kernels over a 4 GiB float64 array: a copy
     (read + write), a sum (read), a fill (write); medians of 10.  The ceiling
@@ -361,6 +496,8 @@ def main():
                          "plain torch kernels reach on this GPU (context for the HBM-bound "
                          "kernels)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workload configurations (C1, C3, C4, C5)")
     ap.add_argument("--profile-only", choices=["fp32_polish", "fp64"], default=None,
                     help="run only the timed steps of one form (for profilers)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -493,37 +630,44 @@ def main():
         log(f"{form}: separate launches: step {sep_ms:.3f} ms, solve {solve_ms:.3f} ms, "
             f"density {dens_ms:.3f} ms")
 
-        # context: the same fused launch with Alg. 1's shift (the bottom-right
-        # entry) in place of the default Wilkinson shift
+        # the same step with Alg. 1's own shift (the bottom-right entry,
+        # PR_FLAG_RAYLEIGH_SHIFT) in place of the default rule
         _, _, its_r = pr.solve(a, None, form, iter_counts=True, roots=roots, status=status,
                                flags=pr.FLAG_RAYLEIGH_SHIFT)
         torch.cuda.synchronize()
         its_r = its_r.cpu().numpy()
 
-        def bin_rayleigh():
+        def step_rayleigh(e=None):
             hist.zero_()
+            if e: e[0].record(stream)
             pr.solve_bin(a, win, shape, None, form, roots=roots, status=status, out=hist,
                          flags=pr.FLAG_RAYLEIGH_SHIFT)
+            if e: e[1].record(stream)
+            pr.backward(a, roots, cot, None, status, grad_coeffs=gcoef)
 
         for _ in range(args.warmup):
-            bin_rayleigh()
+            step_rayleigh()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            bin_rayleigh()
-        e1.record(stream)
+        evr = [[torch.cuda.Event(enable_timing=True) for _ in range(2)]
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step_rayleigh(evr[k])
         torch.cuda.synchronize()
-        ray_ms = e0.elapsed_time(e1) / args.steps
+        ray_step = (time.perf_counter() - t0) * 1e3 / args.steps
+        ray_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evr]))
         fl_r = algorithmic_flops(its_r, shift=0, start=0) + (n * polish_flops(6, 2)
                                                     if form == "fp32_polish" else 0)
         res[form]["paper_shift"] = dict(
-            zero_and_solve_bin_ms=ray_ms, mean_qr_steps=float(its_r.sum(axis=0).mean()),
+            step_ms=ray_step, polys_per_s=n / (ray_step * 1e-3), solve_bin_ms=ray_ms,
+            mean_qr_steps=float(its_r.sum(axis=0).mean()),
             alg_tflops=fl_r / (ray_ms * 1e-3) / 1e12,
-            note="PR_FLAG_RAYLEIGH_SHIFT: Alg. 1's bottom-entry shift; image clear + "
-                 "solve_bin per step, no backward")
-        log(f"{form}: with Alg. 1's shift: clear + solve+bin {ray_ms:.3f} ms, "
+            frac_of_peak=fl_r / (ray_ms * 1e-3) / (PEAK_FP32 if form == "fp32_polish"
+                                                    else PEAK_FP64),
+            flagged_frac=float((status.cpu().numpy() != 0).mean()),
+            note="PR_FLAG_RAYLEIGH_SHIFT: Alg. 1's bottom-entry shift; the same step (image "
+                 "clear, solve_bin, backward)")
+        log(f"{form}: with Alg. 1's shift: step {ray_step:.3f} ms, solve+bin {ray_ms:.3f} ms, "
             f"{its_r.sum(axis=0).mean():.2f} steps per polynomial")
 
     main_form = forms[0]
@@ -546,7 +690,10 @@ def main():
         "config": {"workload": f"parametric grid {g}x{g}: {n} monic degree-6 complex polynomials "
                                "a_k = c_k + t1 d_k + t2 e_k, 1920x1080 int32 density image, "
                                "step = solve with density binning in one launch + backward",
-                   "n_polys": n, "degree": 6, "image": [1920, 1080], "form": main_form},
+                   "n_polys": n, "degree": 6, "image": [1920, 1080], "form": main_form,
+                   "shift": "default rule: Wilkinson's shift (eigenvalue of the trailing 2x2 "
+                            "block nearest its bottom entry), first step from the quadratic "
+                            "start; Alg. 1's bottom-entry shift reported as alg1_shift"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(main_form, g),
@@ -561,6 +708,15 @@ def main():
         out["solve_ratio_fp32polish_over_fp64"] = (res["fp64"]["solve_bin_ms"] /
                                                    res["fp32_polish"]["solve_bin_ms"])
         out["step_ratio_fp32polish_over_fp64"] = res["fp64"]["step_ms"] / res["fp32_polish"]["step_ms"]
+        # the headline's step under Alg. 1's own shift, both forms
+        p32, p64 = res["fp32_polish"]["paper_shift"], res["fp64"]["paper_shift"]
+        out["alg1_shift"] = {
+            "fp32_polish_polys_per_s": p32["polys_per_s"], "fp64_polys_per_s": p64["polys_per_s"],
+            "fp32_polish_step_ms": p32["step_ms"], "fp64_step_ms": p64["step_ms"],
+            "solve_ratio_fp32polish_over_fp64": p64["solve_bin_ms"] / p32["solve_bin_ms"],
+            "step_ratio_fp32polish_over_fp64": p64["step_ms"] / p32["step_ms"],
+            "fp32_polish_frac_of_fp32_peak": p32["frac_of_peak"],
+            "fp64_frac_of_fp64_peak": p64["frac_of_peak"]}
     if args.profile_only is None:
         # paper-literal mode (Alg. 2): exactly T = 10 QR steps per level, FP32
         # sweeps as in the paper's implementations; reported as context
@@ -613,6 +769,10 @@ def main():
                           if eu.size else None,
                           "flagged": int((~ok).sum()), "checked_polys": int(sel.size)}
         out["accuracy_vs_oracle"] = errs
+    if not args.no_configs and args.profile_only is None:
+        del a, cot, roots, status, gcoef, hist
+        torch.cuda.empty_cache()
+        out.update(config_legs(args, torch, workloads, pr, dev))
     print(json.dumps(out))
 
 

@@ -34,6 +34,22 @@ DMAX = 6
 SQRT_HALF = np.sqrt(0.5)
 
 
+def _par_cols(n: int, fn, min_chunk: int = 1 << 19) -> None:
+    """Run fn(s, e) over column ranges that cover [0, n), on a thread pool
+    (numpy's elementwise routines release the interpreter lock).  Only
+    deterministic elementwise work goes through here -- never a random
+    draw -- so every value is the one a single whole-array call gives."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    workers = min(16, os.cpu_count() or 1)
+    if n <= min_chunk or workers == 1:
+        fn(0, n)
+        return
+    step = max(min_chunk, -(-n // (4 * workers)))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda s: fn(s, min(n, s + step)), range(0, n, step)))
+
+
 def _cn(rng, shape):
     x = rng.standard_normal((2,) + tuple(shape))
     return (x[0] + 1j * x[1]) * SQRT_HALF
@@ -78,13 +94,20 @@ def mixed(n: int, seed: int = 0):
     moduli log-uniform over [1e-2, 1e2], phases uniform."""
     rng = np.random.default_rng(seed)
     deg = rng.integers(2, DMAX + 1, n).astype(np.int32)
-    mag = 10.0 ** rng.uniform(-2.0, 2.0, (DMAX, n))
+    lmag = rng.uniform(-2.0, 2.0, (DMAX, n))
     ph = rng.uniform(0.0, 2.0 * np.pi, (DMAX, n))
     a = np.zeros((DMAX + 1, n), dtype=np.complex128)
-    a[:DMAX] = mag * (np.cos(ph) + 1j * np.sin(ph))
     k = np.arange(DMAX + 1)[:, None]
-    a[k > deg[None, :]] = 0.0
-    a[k == deg[None, :]] = 1.0
+
+    def fill(s, e):
+        blk = a[:, s:e]
+        p = ph[:, s:e]
+        blk[:DMAX] = 10.0 ** lmag[:, s:e] * (np.cos(p) + 1j * np.sin(p))
+        dd = deg[None, s:e]
+        blk[k > dd] = 0.0
+        blk[k == dd] = 1.0
+
+    _par_cols(n, fill)
     return a, deg
 
 
@@ -92,16 +115,23 @@ def expand_roots(roots: np.ndarray) -> np.ndarray:
     """Coefficients [d+1, n] (row k = a_k, a_d = 1) of prod_j (z - r_j),
     expanded in x87 extended precision and rounded once to complex128.
     ``roots`` is [d, n]."""
-    r = np.asarray(roots).astype(np.clongdouble)
-    d, n = r.shape
-    c = np.zeros((d + 1, n), dtype=np.clongdouble)
-    c[0] = 1.0                                 # c[k] = coefficient of z^k so far (degree 0)
-    for j in range(d):
-        # multiply current polynomial by (z - r_j)
-        shifted = np.zeros_like(c)
-        shifted[1:] = c[:-1]
-        c = shifted - r[j][None, :] * c
-    return c.astype(np.complex128)
+    roots = np.asarray(roots)
+    d, n = roots.shape
+    out = np.empty((d + 1, n), dtype=np.complex128)
+
+    def expand(s, e):
+        r = roots[:, s:e].astype(np.clongdouble)
+        c = np.zeros((d + 1, e - s), dtype=np.clongdouble)
+        c[0] = 1.0                             # c[k] = coefficient of z^k so far (degree 0)
+        for j in range(d):
+            # multiply current polynomial by (z - r_j)
+            shifted = np.zeros_like(c)
+            shifted[1:] = c[:-1]
+            c = shifted - r[j][None, :] * c
+        out[:, s:e] = c.astype(np.complex128)
+
+    _par_cols(n, expand)
+    return out
 
 
 def _uniform_disk(rng, shape, rmin2=0.0, rmax2=1.0):
