@@ -54,7 +54,9 @@ enum pr_error {
     PR_OK = 0,
     PR_ERR_INVALID_ARG = -1,  /* a NULL pointer, n < 0, dmax out of range, bad window, ... */
     PR_ERR_UNSUPPORTED = -2,  /* option value the library does not implement */
-    PR_ERR_HIP = -3           /* the HIP runtime refused the launch */
+    PR_ERR_HIP = -3,          /* the HIP runtime refused the launch */
+    PR_ERR_NO_MEMORY = -4     /* the caller's workspace is missing or smaller than the call
+                                 needs (the library itself never allocates) */
 };
 
 /* Per-polynomial status bits (uint32).  0 = every root computed normally. */
@@ -178,6 +180,51 @@ int pr_solve(const pr_complex* coeffs, const int32_t* degrees, int64_t n, int32_
 int pr_density(const pr_complex* roots, const int32_t* degrees, const uint32_t* status,
                uint32_t skip_mask, int64_t n, int32_t dmax, double x0, double x1, double y0,
                double y1, int32_t width, int32_t height, int32_t* hist, void* stream);
+
+/*
+ * pr_density_sorted -- pr_density for roots spread over the image, counted
+ * per image tile in on-chip memory (Sec. III: roots converted to pixel
+ * coordinates and accumulated in video memory).
+ *
+ * Same arguments, pixel rule and result as pr_density: the counts added to
+ * hist are identical bit for bit (every pixel decision is the same FP64
+ * arithmetic and integer addition does not depend on order).  Instead of one
+ * device-wide atomic per root, the roots' pixel indices are first grouped by
+ * image tile (tiles of 2^14 consecutive row-major pixels) with a counting
+ * sort into `workspace` (no atomics: the sorted order is deterministic), each
+ * tile is counted in an on-chip histogram, and each pixel of the image is
+ * updated once, by one thread.  This pays off
+ * when the roots of neighbouring polynomials fall on different pixels (e.g.
+ * random coefficients); for smooth families whose neighbours share pixels
+ * pr_density's wave-merged atomics are as fast.
+ *
+ *   workspace        DEVICE memory owned by the caller, 256-byte aligned,
+ *                    of at least pr_density_sorted_workspace(n, dmax, width,
+ *                    height) bytes; its contents on entry do not matter and
+ *                    on return are unspecified.  Calls that share a
+ *                    workspace must not overlap in time.
+ *   workspace_bytes  its size in bytes.
+ * Images of more than 2^24 pixels, and batches with dmax * n >= 2^31, need
+ * no workspace (the required size is 0): they are counted as by pr_density.
+ * Errors: those of pr_density; PR_ERR_NO_MEMORY when the workspace is NULL
+ * or smaller than required, PR_ERR_INVALID_ARG when it is not 256-byte
+ * aligned.  The call enqueues five kernels on `stream`.
+ */
+int pr_density_sorted(const pr_complex* roots, const int32_t* degrees, const uint32_t* status,
+                      uint32_t skip_mask, int64_t n, int32_t dmax, double x0, double x1,
+                      double y0, double y1, int32_t width, int32_t height, int32_t* hist,
+                      void* workspace, int64_t workspace_bytes, void* stream);
+
+/*
+ * pr_density_sorted_workspace -- bytes of workspace pr_density_sorted needs
+ * for n polynomials of row count dmax and a width x height image: about
+ * 6 * dmax * n (a pixel index and a sorted 16-bit offset per root slot),
+ * plus 64 KiB per partial tile histogram (at most the tile count plus 512)
+ * and at most 512 KiB of per-tile bookkeeping.  0 when no workspace is
+ * needed; PR_ERR_INVALID_ARG (negative) for n < 0, dmax outside 1..6, or an
+ * empty or over-large image.  A HOST call: nothing is enqueued.
+ */
+int64_t pr_density_sorted_workspace(int64_t n, int32_t dmax, int32_t width, int32_t height);
 
 /*
  * pr_solve_bin -- solve and count in one launch (Sec. III: each eigenvalue

@@ -146,11 +146,12 @@ extern "C" int pr_solve_bin(const pr_complex* coeffs, const int32_t* degrees, in
     return solve_common(coeffs, degrees, n, dmax, roots, status, opts, &w, skip_mask, stream);
 }
 
-static int density_common(const pr_complex* roots, const int32_t* degrees,
-                          const uint32_t* status, uint32_t skip_mask, int64_t n, int32_t dmax,
-                          double x0, double x1, double y0, double y1, int32_t width,
-                          int32_t height, int32_t* hist, const pr_complex* centers,
-                          const double* radii, double rmax2, void* stream)
+// Argument checks shared by the density entry points; fills `a` (a.n == 0:
+// nothing to enqueue).
+static int density_args(const pr_complex* roots, const int32_t* degrees, const uint32_t* status,
+                        uint32_t skip_mask, int64_t n, int32_t dmax, double x0, double x1,
+                        double y0, double y1, int32_t width, int32_t height, int32_t* hist,
+                        DensityArgs& a)
 {
     if (n < 0 || dmax < 1 || dmax > 6)
         return PR_ERR_INVALID_ARG;
@@ -160,11 +161,8 @@ static int density_common(const pr_complex* roots, const int32_t* degrees,
     const int rc = make_window(x0, x1, y0, y1, width, height, hist, w);
     if (rc != PR_OK)
         return rc;
-    if (n == 0)
-        return PR_OK;
     if (n > kMaxDensityBatch)
         return PR_ERR_INVALID_ARG;
-    DensityArgs a;
     a.roots = roots;
     a.degrees = degrees;
     a.status = status;
@@ -172,10 +170,10 @@ static int density_common(const pr_complex* roots, const int32_t* degrees,
     a.n = n;
     a.dmax = dmax;
     a.win = w;
-    a.centers = centers;
-    a.radii = radii;
-    a.rmax2 = rmax2;
-    return hip_status(launch_density(a, static_cast<hipStream_t>(stream)));
+    a.centers = nullptr;
+    a.radii = nullptr;
+    a.rmax2 = 0.0;
+    return PR_OK;
 }
 
 extern "C" int pr_density(const pr_complex* roots, const int32_t* degrees,
@@ -183,8 +181,43 @@ extern "C" int pr_density(const pr_complex* roots, const int32_t* degrees,
                           double x0, double x1, double y0, double y1, int32_t width,
                           int32_t height, int32_t* hist, void* stream)
 {
-    return density_common(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
-                          height, hist, nullptr, nullptr, 0.0, stream);
+    DensityArgs a;
+    const int rc = density_args(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
+                                height, hist, a);
+    if (rc != PR_OK || n == 0)
+        return rc;
+    return hip_status(launch_density(a, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" int64_t pr_density_sorted_workspace(int64_t n, int32_t dmax, int32_t width,
+                                               int32_t height)
+{
+    if (n < 0 || dmax < 1 || dmax > 6 || width <= 0 || height <= 0 ||
+        (int64_t)width * (int64_t)height > 0x7fffffffLL || n > kMaxDensityBatch)
+        return PR_ERR_INVALID_ARG;
+    return sortbin_workspace(n, dmax, width, height);
+}
+
+extern "C" int pr_density_sorted(const pr_complex* roots, const int32_t* degrees,
+                                 const uint32_t* status, uint32_t skip_mask, int64_t n,
+                                 int32_t dmax, double x0, double x1, double y0, double y1,
+                                 int32_t width, int32_t height, int32_t* hist, void* workspace,
+                                 int64_t workspace_bytes, void* stream)
+{
+    DensityArgs a;
+    const int rc = density_args(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
+                                height, hist, a);
+    if (rc != PR_OK || n == 0)
+        return rc;
+    const int64_t need = sortbin_workspace(n, dmax, width, height);
+    if (need > 0) {
+        if (!workspace || workspace_bytes < need)
+            return PR_ERR_NO_MEMORY;
+        if (reinterpret_cast<uintptr_t>(workspace) & 255)
+            return PR_ERR_INVALID_ARG;
+    }
+    return hip_status(
+        launch_density_sorted(a, workspace, cu_count(), static_cast<hipStream_t>(stream)));
 }
 
 extern "C" int pr_density_local(const pr_complex* roots, const int32_t* degrees,
@@ -197,8 +230,15 @@ extern "C" int pr_density_local(const pr_complex* roots, const int32_t* degrees,
         return PR_ERR_INVALID_ARG;
     if (n > 0 && (!centers || !radii))
         return PR_ERR_INVALID_ARG;
-    return density_common(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
-                          height, hist, centers, radii, rmax2, stream);
+    DensityArgs a;
+    const int rc = density_args(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
+                                height, hist, a);
+    if (rc != PR_OK || n == 0)
+        return rc;
+    a.centers = centers;
+    a.radii = radii;
+    a.rmax2 = rmax2;
+    return hip_status(launch_density(a, static_cast<hipStream_t>(stream)));
 }
 
 extern "C" int pr_l2fit_nodes(int32_t nr, int32_t nt, double* nodes, double* weights)
@@ -270,6 +310,7 @@ extern "C" const char* pr_strerror(int code)
     case PR_ERR_INVALID_ARG: return "invalid argument";
     case PR_ERR_UNSUPPORTED: return "unsupported option";
     case PR_ERR_HIP: return "HIP runtime error";
+    case PR_ERR_NO_MEMORY: return "workspace too small for this call";
     }
     return "unknown error code";
 }

@@ -68,6 +68,12 @@ struct DensityArgs {
 
 hipError_t launch_density(const DensityArgs& a, hipStream_t stream);
 
+// Tile-sorted counting (sortbin.hip): bytes of workspace a batch needs (0:
+// counted by launch_density, no workspace), and the launches.
+int64_t sortbin_workspace(int64_t n, int dmax, int width, int height);
+hipError_t launch_density_sorted(const DensityArgs& a, void* workspace, int cus,
+                                 hipStream_t stream);
+
 struct BackwardArgs {
     const pr_complex* coeffs;
     const int32_t* degrees;

@@ -224,3 +224,41 @@ def test_committed_tuning_cache_is_valid():
         assert -1 <= o.get("tile", 0) <= 4096
         assert o.get("grid_blocks", 0) >= 0
         assert 1 <= o.get("max_iter_per_level", 30) <= 1000
+
+
+def test_density_sorted_workspace_and_argument_validation(lib):
+    """Workspace sizes (a host call) and the checks pr_density_sorted makes
+    before anything is enqueued."""
+    import paper_2507_02164_amd as pr
+    f = ctypes.c_void_p(0x1000)
+    W = lib.pr_density_sorted_workspace
+    assert W(-1, 6, 8, 8) == pr.PR_ERR_INVALID_ARG
+    assert W(10, 0, 8, 8) == pr.PR_ERR_INVALID_ARG
+    assert W(10, 7, 8, 8) == pr.PR_ERR_INVALID_ARG
+    assert W(10, 6, 0, 8) == pr.PR_ERR_INVALID_ARG
+    assert W(10, 6, 65536, 65536) == pr.PR_ERR_INVALID_ARG
+    assert W(0, 6, 256, 256) == 0
+    # beyond 2^24 pixels (or 2^31 roots) the call counts directly: no workspace
+    assert W(1000, 6, 8192, 4096) == 0
+    assert W(2 ** 29, 6, 256, 256) == 0
+    # the sorted offsets take 2 bytes per root slot, the partial tiles 64 KiB each
+    w1, w2 = W(1000, 6, 1920, 1080), W(2000, 6, 1920, 1080)
+    assert w1 > 2 * 6 * 1000 and w2 - w1 >= 2 * 6 * 1000 and w1 % 256 == 0
+    assert W(1 << 24, 6, 1920, 1080) >= 2 * 6 * (1 << 24) + 127 * 65536
+
+    need = W(4, 6, 8, 8)
+
+    def call(ws=f, nbytes=need, roots=f, hist=f, n=4, dmax=6, w=8, h=8, x1=1.0):
+        return lib.pr_density_sorted(roots, None, None, 0, n, dmax, -1.0, x1, -1.0, 1.0, w, h, hist,
+                                     ws, nbytes, None)
+
+    assert call(ws=None) == pr.PR_ERR_NO_MEMORY
+    assert call(nbytes=need - 1) == pr.PR_ERR_NO_MEMORY
+    assert call(ws=ctypes.c_void_p(0x1010)) == pr.PR_ERR_INVALID_ARG     # not 256-aligned
+    assert call(roots=None) == pr.PR_ERR_INVALID_ARG
+    assert call(hist=None) == pr.PR_ERR_INVALID_ARG
+    assert call(dmax=0) == pr.PR_ERR_INVALID_ARG
+    assert call(x1=-2.0) == pr.PR_ERR_INVALID_ARG
+    assert call(n=-1) == pr.PR_ERR_INVALID_ARG
+    assert call(n=0, ws=None, nbytes=0) == pr.PR_OK
+    assert pr.strerror(pr.PR_ERR_NO_MEMORY).startswith("workspace")
