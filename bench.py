@@ -427,6 +427,40 @@ def config_legs(args, torch, workloads, pr, dev):
     out["c5_clustered16Mi"] = c5
     del a, r, s, h
     torch.cuda.empty_cache()
+
+    # the two density paths on 16Mi polynomials' roots at 1920 x 1080: spread
+    # roots (Gaussian coefficients, 100M roots over [-3,3)^2) and the
+    # parametric grid's (neighbours share pixels); images compared bit for bit
+    dens = {}
+    for name, make, win in (
+            ("gaussian16Mi", lambda: workloads.gaussian(16 * 2 ** 20, 0), workloads.GAUSSIAN_WINDOW),
+            ("parametric4096", lambda: workloads.parametric(4096, 0), workloads.PARAMETRIC_WINDOW)):
+        log(f"density paths: {name}")
+        a = torch.from_numpy(make()).to(dev)
+        n = a.shape[1]
+        r, s = pr.solve(a, None, "fp32_polish")
+        del a
+        shape = (1920, 1080)
+        h1 = torch.zeros((1080, 1920), dtype=torch.int32, device=dev)
+        h2 = torch.zeros_like(h1)
+        ws = torch.empty((max(pr.density_sorted_workspace(n, 6, *shape), 1),), dtype=torch.uint8,
+                         device=dev)
+        d_ms = _median_ms(torch, lambda: (h1.zero_(), pr.density(r, win, shape, status=s, out=h1)),
+                          reps, warm)
+        s_ms = _median_ms(torch, lambda: (h2.zero_(), pr.density_sorted(r, win, shape, status=s,
+                                                                        out=h2, workspace=ws)),
+                          reps, warm)
+        nroots = int(h1.sum())
+        dens[name] = {"n_polys": n, "roots_counted": nroots, "direct_ms": d_ms, "sorted_ms": s_ms,
+                      "direct_roots_per_s": nroots / (d_ms * 1e-3),
+                      "sorted_roots_per_s": nroots / (s_ms * 1e-3),
+                      "sorted_alg_GBps": 16 * 6 * n / (s_ms * 1e-3) / 1e9,
+                      "workspace_bytes": int(ws.numel()),
+                      "images_equal": bool(torch.equal(h1, h2))}
+        log(f"density paths: {name}: direct {d_ms:.3f} ms, sorted {s_ms:.3f} ms")
+        del r, s, h1, h2, ws
+        torch.cuda.empty_cache()
+    out["density_paths_1080p"] = dens
     return out
 
 
