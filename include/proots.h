@@ -227,6 +227,28 @@ int pr_density_sorted(const pr_complex* roots, const int32_t* degrees, const uin
 int64_t pr_density_sorted_workspace(int64_t n, int32_t dmax, int32_t width, int32_t height);
 
 /*
+ * pr_density_sorted_noalloc -- pr_density_sorted without a workspace
+ * argument, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * Same arguments (less workspace and workspace_bytes), result and errors as
+ * pr_density_sorted.  The workspace is instead a static array of 64 MiB
+ * (2^26 bytes) in the library, one per GPU, held from the first call on
+ * that GPU until the process ends; the call itself allocates nothing.  A
+ * batch whose pr_density_sorted_workspace exceeds 2^26 bytes (about 1.2M
+ * degree-6 polynomials for a 1920 x 1080 image) is refused with
+ * PR_ERR_NO_MEMORY: split it into several calls on the same image.  PR_ERR_HIP if the array's device address cannot be
+ * looked up.  Every call on one GPU uses that GPU's array (no state carries
+ * from one call to the next: each region is written before it is read), so
+ * calls that overlap in time on one GPU -- on different streams or from
+ * different host threads -- race and must not be issued.
+ */
+int pr_density_sorted_noalloc(const pr_complex* roots, const int32_t* degrees,
+                              const uint32_t* status, uint32_t skip_mask, int64_t n,
+                              int32_t dmax, double x0, double x1, double y0, double y1,
+                              int32_t width, int32_t height, int32_t* hist, void* stream);
+
+/*
  * pr_solve_bin -- solve and count in one launch (Sec. III: each eigenvalue
  * goes straight from the solver to its pixel count, the roots need not be
  * kept).

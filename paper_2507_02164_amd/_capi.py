@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         L.pr_backward.restype = ctypes.c_int
         L.pr_density_sorted.argtypes = [P, P, P, U32, I64, I32, D, D, D, D, I32, I32, P, P, I64, P]
         L.pr_density_sorted.restype = ctypes.c_int
+        L.pr_density_sorted_noalloc.argtypes = [P, P, P, U32, I64, I32, D, D, D, D, I32, I32, P, P]
+        L.pr_density_sorted_noalloc.restype = ctypes.c_int
         L.pr_density_sorted_workspace.argtypes = [I64, I32, I32, I32]
         L.pr_density_sorted_workspace.restype = ctypes.c_int64
         L.pr_density_local.argtypes = [P, P, P, U32, I64, I32, P, P, D, D, D, D, D, I32, I32, P, P]
@@ -282,6 +284,39 @@ def density_sorted(roots, window, shape, degrees=None, status=None, skip_mask=0,
                                      _ptr(out), _ptr(workspace), workspace.numel(), _stream(stream))
     if rc != PR_OK:
         raise ProotsError(rc, "pr_density_sorted")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 1 << 26   # the static per-GPU array of pr_density_sorted_noalloc
+
+
+def density_sorted_noalloc(roots, window, shape, degrees=None, status=None, skip_mask=0,
+                           out=None, stream=None):
+    """``density_sorted`` through the allocation-free entry point
+    (pr_density_sorted_noalloc): the library's static per-GPU scratch array
+    serves as the workspace, so the call allocates nothing (``out`` must then
+    be given by callers that cannot allocate).  Batches needing more than
+    NOALLOC_SCRATCH_BYTES raise ProotsError(PR_ERR_NO_MEMORY); calls that
+    overlap on one GPU race."""
+    _check(roots, "roots", torch.complex128)
+    if roots.dim() != 2:
+        raise ValueError("roots must be 2-D [dmax, n]")
+    dmax, n = roots.shape
+    x0, x1, y0, y1 = (float(v) for v in window)
+    width, height = (int(v) for v in shape)
+    if out is None:
+        out = torch.zeros((height, width), dtype=torch.int32, device=roots.device)
+    _check(out, "out", torch.int32, (height, width), device=roots.device)
+    if degrees is not None:
+        _check(degrees, "degrees", torch.int32, (n,), device=roots.device)
+    if status is not None:
+        _check(status, "status", torch.int32, (n,), device=roots.device)
+    with torch.cuda.device(roots.device):
+        rc = lib().pr_density_sorted_noalloc(_ptr(roots), _ptr(degrees), _ptr(status),
+                                             skip_mask & 0xFFFFFFFF, n, dmax, x0, x1, y0, y1, width,
+                                             height, _ptr(out), _stream(stream))
+    if rc != PR_OK:
+        raise ProotsError(rc, "pr_density_sorted_noalloc")
     return out
 
 

@@ -220,6 +220,26 @@ extern "C" int pr_density_sorted(const pr_complex* roots, const int32_t* degrees
         launch_density_sorted(a, workspace, cu_count(), static_cast<hipStream_t>(stream)));
 }
 
+extern "C" int pr_density_sorted_noalloc(const pr_complex* roots, const int32_t* degrees,
+                                         const uint32_t* status, uint32_t skip_mask, int64_t n,
+                                         int32_t dmax, double x0, double x1, double y0,
+                                         double y1, int32_t width, int32_t height, int32_t* hist,
+                                         void* stream)
+{
+    DensityArgs a;
+    const int rc = density_args(roots, degrees, status, skip_mask, n, dmax, x0, x1, y0, y1, width,
+                                height, hist, a);
+    if (rc != PR_OK || n == 0)
+        return rc;
+    const int64_t need = sortbin_workspace(n, dmax, width, height);
+    if (need > kSortScratchBytes)
+        return PR_ERR_NO_MEMORY;
+    void* ws = nullptr;
+    if (need > 0 && (ws = sortbin_scratch()) == nullptr)
+        return PR_ERR_HIP;
+    return hip_status(launch_density_sorted(a, ws, cu_count(), static_cast<hipStream_t>(stream)));
+}
+
 extern "C" int pr_density_local(const pr_complex* roots, const int32_t* degrees,
                                 const uint32_t* status, uint32_t skip_mask, int64_t n,
                                 int32_t dmax, const pr_complex* centers, const double* radii,
@@ -310,7 +330,7 @@ extern "C" const char* pr_strerror(int code)
     case PR_ERR_INVALID_ARG: return "invalid argument";
     case PR_ERR_UNSUPPORTED: return "unsupported option";
     case PR_ERR_HIP: return "HIP runtime error";
-    case PR_ERR_NO_MEMORY: return "workspace too small for this call";
+    case PR_ERR_NO_MEMORY: return "workspace (or the static scratch of an allocation-free call) too small for this call";
     }
     return "unknown error code";
 }

@@ -74,6 +74,11 @@ int64_t sortbin_workspace(int64_t n, int dmax, int width, int height);
 hipError_t launch_density_sorted(const DensityArgs& a, void* workspace, int cus,
                                  hipStream_t stream);
 
+// The allocation-free variant's static per-GPU workspace: its size, and its
+// device address on the current GPU (nullptr if the lookup fails).
+constexpr int64_t kSortScratchBytes = (int64_t)64 << 20;
+void* sortbin_scratch();
+
 struct BackwardArgs {
     const pr_complex* coeffs;
     const int32_t* degrees;

@@ -49,6 +49,8 @@
 // counted by the direct kernel instead (no workspace).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "bin.hpp"
 #include "internal.hpp"
 
@@ -479,7 +481,30 @@ hipError_t launch_dm(const DensityArgs& a, const Plan& p, void* ws, int cus, hip
     return hipGetLastError();
 }
 
+// The allocation-free entry point's workspace: one array per GPU, kept until
+// the process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code the name stands for a host-side shadow, not a device address);
+// it passes the device address hipGetSymbolAddress returns for the GPU that
+// is current, looked up on the first call on each GPU.
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kSortScratchBytes];
+
 }  // namespace
+
+void* sortbin_scratch()
+{
+    static std::atomic<void*> address[kMaxScratchDevices];
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices)
+        return nullptr;
+    void* ptr = address[dev].load(std::memory_order_acquire);
+    if (ptr == nullptr) {
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+            return nullptr;
+        address[dev].store(ptr, std::memory_order_release);
+    }
+    return ptr;
+}
 
 int64_t sortbin_workspace(int64_t n, int dmax, int width, int height)
 {
