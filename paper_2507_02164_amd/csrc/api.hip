@@ -8,6 +8,7 @@
 
 #include "internal.hpp"
 #include "proots.h"
+#include "validate.hpp"
 
 using namespace proots;
 
@@ -47,18 +48,10 @@ int cu_count()
 static int make_window(double x0, double x1, double y0, double y1, int32_t width,
                        int32_t height, int32_t* hist, BinWindow& w)
 {
-    if (!hist)
-        return PR_ERR_INVALID_ARG;
-    if (!std::isfinite(x0) || !std::isfinite(x1) || !std::isfinite(y0) || !std::isfinite(y1))
-        return PR_ERR_INVALID_ARG;
-    if (!(x1 > x0) || !(y1 > y0) || width <= 0 || height <= 0)
-        return PR_ERR_INVALID_ARG;
-    if ((int64_t)width * (int64_t)height > 0x7fffffffLL)
-        return PR_ERR_INVALID_ARG;
-    const double sx = (double)width / (x1 - x0);
-    const double sy = (double)height / (y1 - y0);
-    if (!std::isfinite(sx) || !std::isfinite(sy))
-        return PR_ERR_INVALID_ARG;
+    double sx = 0.0, sy = 0.0;
+    const int rc = check_window(x0, x1, y0, y1, width, height, hist, sx, sy);
+    if (rc != PR_OK)
+        return rc;
     w.x0 = x0;
     w.y0 = y0;
     w.sx = sx;
@@ -75,27 +68,14 @@ static int solve_common(const pr_complex* coeffs, const int32_t* degrees, int64_
                         const pr_solve_opts* opts, const BinWindow* win, uint32_t skip_mask,
                         void* stream)
 {
-    if (n < 0 || dmax < 1 || dmax > 6)
+    if (check_batch(n, dmax) != PR_OK)
         return PR_ERR_INVALID_ARG;
     if (n > 0 && (!coeffs || (!roots && !win) || !status))
         return PR_ERR_INVALID_ARG;
-    pr_solve_opts o{};
-    if (opts)
-        o = *opts;
-    if (o.precision != PR_FP64 && o.precision != PR_FP32_POLISH)
-        return PR_ERR_UNSUPPORTED;
-    if (o.max_iter_per_level < 0 || o.max_iter_per_level > 1000)
-        return PR_ERR_INVALID_ARG;
-    if (o.polish_steps < 0 || o.polish_steps > 8)
-        return PR_ERR_INVALID_ARG;
-    if (!(o.polish_tol >= 0.0 && o.polish_tol < 1.0))
-        return PR_ERR_INVALID_ARG;
-    if (o.flags &
-        ~(uint32_t)(PR_FLAG_NO_EXCEPTIONAL_SHIFT | PR_FLAG_FIXED_STEPS | PR_FLAG_FP64_FALLBACK |
-                    PR_FLAG_RAYLEIGH_SHIFT))
-        return PR_ERR_UNSUPPORTED;
-    if (o.tile < -1 || o.tile > max_tile() || o.grid_blocks < 0)
-        return PR_ERR_INVALID_ARG;
+    pr_solve_opts o;
+    const int orc = check_solve_opts(opts, max_tile(), o);
+    if (orc != PR_OK)
+        return orc;
     if (n == 0)
         return PR_OK;
     if (n > kMaxSolveBatch)
@@ -153,7 +133,7 @@ static int density_args(const pr_complex* roots, const int32_t* degrees, const u
                         double y0, double y1, int32_t width, int32_t height, int32_t* hist,
                         DensityArgs& a)
 {
-    if (n < 0 || dmax < 1 || dmax > 6)
+    if (check_batch(n, dmax) != PR_OK)
         return PR_ERR_INVALID_ARG;
     if (n > 0 && !roots)
         return PR_ERR_INVALID_ARG;

@@ -53,25 +53,18 @@
 
 #include "bin.hpp"
 #include "internal.hpp"
+#include "sortplan.hpp"
 
 namespace proots {
 namespace {
 
-constexpr int kTileShift = 14;
-constexpr int kTilePixels = 1 << kTileShift;  // 64 KiB of LDS counters
-constexpr uint32_t kTileMask = kTilePixels - 1;
-constexpr int kMaxTiles = 1024;               // images up to 2^24 pixels
+using namespace sortbin;
+
 constexpr int kCountBlock = 512;
 constexpr int kPlanBlock = 1024;               // >= kMaxTiles and >= kMaxBlocks
-constexpr int kScatterBlock = 1024;
+constexpr int kScatterBlock = kChunk;
 constexpr int kAccBlock = 1024;
 constexpr int kReduceBlock = 256;
-constexpr int kChunk = kScatterBlock;        // polynomials per chunk
-constexpr int kMaxBlocks = 1024;              // count/scatter blocks
-constexpr int64_t kMinSegment = 1 << 16;
-constexpr int64_t kSegmentsPerBatch = 512;
-
-inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 // Lanes of a wave that add to the same LDS counter serialise on it.  Roots of
 // a smooth family (neighbouring polynomials) land on the same tile, often on
@@ -141,40 +134,6 @@ __device__ __forceinline__ void lds_add(uint32_t* c, int idx, uint32_t amt)
     }
     if (idx >= 0)
         atomicAdd(&c[idx], amt);
-}
-
-struct Plan {
-    int ntiles;
-    int nblocks;           // count and scatter blocks
-    int64_t nchunks;       // chunks of kChunk polynomials (the last may hold fewer)
-    int64_t roots_bound;   // dmax n
-    uint32_t seg_len;
-    int64_t max_segments;
-    int64_t ctrl_bytes, runs_bytes, pix_bytes, sorted_bytes, partial_bytes;
-    bool direct;           // count with the direct kernel, no workspace
-};
-
-Plan make_plan(int64_t n, int dmax, int width, int height)
-{
-    Plan p{};
-    const int64_t npix = (int64_t)width * height;
-    p.ntiles = (int)((npix + kTilePixels - 1) >> kTileShift);
-    p.roots_bound = (int64_t)dmax * n;
-    p.direct = p.ntiles > kMaxTiles || p.roots_bound >= ((int64_t)1 << 31) || n == 0;
-    if (p.direct)
-        return p;
-    p.nchunks = (n + kChunk - 1) / kChunk;
-    p.nblocks = (int)(p.nchunks < kMaxBlocks ? p.nchunks : kMaxBlocks);
-    int64_t len = (p.roots_bound + kSegmentsPerBatch - 1) / kSegmentsPerBatch;
-    len = len < kMinSegment ? kMinSegment : len;
-    p.seg_len = (uint32_t)len;
-    p.max_segments = p.ntiles + (p.roots_bound + len - 1) / len;
-    p.ctrl_bytes = align256((int64_t)12 * (p.ntiles + 1));
-    p.runs_bytes = align256((int64_t)4 * p.ntiles * p.nblocks);
-    p.pix_bytes = align256(4 * p.roots_bound);
-    p.sorted_bytes = align256(2 * p.roots_bound + 16);  // + the last 16-byte group's overhang
-    p.partial_bytes = align256(p.max_segments * kTilePixels * 4);
-    return p;
 }
 
 struct Work {
@@ -508,14 +467,12 @@ void* sortbin_scratch()
 
 int64_t sortbin_workspace(int64_t n, int dmax, int width, int height)
 {
-    const Plan p = make_plan(n, dmax, width, height);
-    return p.direct ? 0
-                    : p.ctrl_bytes + p.runs_bytes + p.pix_bytes + p.sorted_bytes + p.partial_bytes;
+    return sortbin::workspace_bytes(sortbin::make_plan(n, dmax, width, height));
 }
 
 hipError_t launch_density_sorted(const DensityArgs& a, void* ws, int cus, hipStream_t stream)
 {
-    const Plan p = make_plan(a.n, a.dmax, a.win.width, a.win.height);
+    const sortbin::Plan p = sortbin::make_plan(a.n, a.dmax, a.win.width, a.win.height);
     if (p.direct)
         return launch_density(a, stream);
     switch (a.dmax) {
