@@ -126,8 +126,9 @@ typedef struct pr_solve_opts {
                                      that every wave holds one degree (one persistent launch);
                                      0 = library default (2048), -1 = no sorting (index order);
                                      valid -1..4096 */
-    int32_t grid_blocks;          /* tiled launch: number of one-wave blocks that walk the
-                                     tiles (0 = 8 per compute unit); valid >= 0 */
+    int32_t grid_blocks;          /* tiled launch: 0 = one one-wave block per (tile, slice of
+                                     64 same-degree polynomials); > 0 = that many persistent
+                                     one-wave blocks walking the tiles; valid >= 0 */
 } pr_solve_opts;
 
 /*

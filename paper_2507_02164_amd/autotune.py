@@ -4,7 +4,10 @@ For a sample of the caller's workload it times every candidate layout on
 the GPU (HIP events, median of repeats) and keeps the fastest:
 
   * tile         -- polynomials per degree-sorted tile (mixed degrees only),
-  * grid_blocks  -- one-wave blocks of the persistent launch, per compute unit,
+  * grid_blocks  -- the mixed-degree launch's shape: 0 for one wave per (tile,
+                    slice of 64 same-degree polynomials), or the number of
+                    persistent one-wave blocks walking the tiles (tried at
+                    several per compute unit),
   * cap          -- QR steps per level before NOT_CONVERGED; a cap is only
                     eligible if it flags no polynomial of the sample that the
                     default cap of 30 does not flag, and a smaller cap is only
@@ -35,6 +38,7 @@ DEFAULT_CACHE = os.path.join(_HERE, "tuning", "tune_cache.json")
 
 TILES = (512, 1024, 2048, 4096)
 BLOCKS_PER_CU = (8, 16, 32, 64, 128)
+SLICED_TILES = (128, 256, 512, 1024, 2048)
 CAPS = (20, 24, 30)
 DEFAULT_CAP = 30
 CAP_MARGIN = 0.03
@@ -119,6 +123,7 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
             caps.append(cap)
     layouts = [dict(tile=-1)]
     if degrees is not None:
+        layouts += [dict(tile=t, grid_blocks=0) for t in SLICED_TILES]
         layouts += [dict(tile=t, grid_blocks=b * cus) for t in TILES for b in BLOCKS_PER_CU]
     trials = []
     for cap in caps:

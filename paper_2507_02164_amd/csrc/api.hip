@@ -93,9 +93,7 @@ static int solve_common(const pr_complex* coeffs, const int32_t* degrees, int64_
     a.polish_steps = o.polish_steps ? o.polish_steps : kDefaultPolishSteps;
     a.polish_tol = o.polish_tol > 0.0 ? o.polish_tol : kDefaultPolishTol;
     a.tile = o.tile == 0 ? kDefaultTile : (o.tile < 0 ? 0 : o.tile);
-    a.grid_blocks = 0;
-    if (degrees && a.tile > 0)
-        a.grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : kDefaultBlocksPerCU * cu_count();
+    a.grid_blocks = o.grid_blocks;  // 0: one block per (tile, slice)
     a.win = win ? *win : BinWindow{0.0, 0.0, 0.0, 0.0, 0, 0, nullptr};
     a.skip_mask = skip_mask;
     a.fallback_tile = a.tile > 0 ? a.tile : kDefaultTile;

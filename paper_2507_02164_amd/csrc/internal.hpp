@@ -35,7 +35,7 @@ struct SolveArgs {
     int32_t polish_steps;
     double polish_tol;
     int32_t tile;         // > 0 with degrees: persistent degree-bucketed launch
-    int32_t grid_blocks;  // persistent launch: number of one-wave blocks (0 = one per tile)
+    int32_t grid_blocks;  // 0: one one-wave block per (tile, slice); > 0: persistent blocks
     // binning epilogue: win.hist == nullptr for none; else every root of a
     // polynomial whose final status has no bit of skip_mask is counted into
     // win.hist exactly as the density kernel would count it (roots may then

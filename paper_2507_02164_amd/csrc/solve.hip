@@ -45,6 +45,10 @@
 //   * FP32 form: sweeps in FP32, test in FP64, then every root is polished
 //     by Newton steps r <- r - p(r)/p'(r) in FP64 on the original
 //     coefficients.
+//   * Mixed degrees: polynomials are bucketed by degree within tiles of
+//     consecutive indices, so that each wave holds one degree; either one
+//     wave per (tile, slice) (solve_sliced_kernel, the default) or persistent
+//     waves walking the tiles (solve_tiled_kernel).
 //   * Binning epilogue (Sec. III's roots-to-pixels path, optional): once
 //     the status is final, the wave counts every lane's roots with merged
 //     atomics -- the same decisions and counts as the density kernel over
@@ -359,8 +363,14 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int d
     }
     const bool act = here && !done;
     const bool ex = exc && (its == 10 || its == 20);
-    const T ere = (T)((double)h[M - 1][M - 1].re + hh * 0.75);
-    const T eim = (T)((double)h[M - 1][M - 1].im + hh * 0.5);
+    const bool first = here && its == 0 && d == M;
+    m = done ? M - 1 : m;
+    its = done ? 0 : its + (act ? 1 : 0);
+    // The trip in which a level's last lane deflates has no lane left to
+    // step: the whole step, shift included, is skipped (a wave-uniform
+    // branch; the matrix is left as it is, as the masked step would leave it).
+    if (!__ballot(act))
+        return;
     cx<T> mu = h[M - 1][M - 1];
     if (wilk) {  // wave-uniform: a scalar branch
         const cx<T> w = wilkinson(h[M - 2][M - 2], h[M - 2][M - 1], h[M - 1][M - 2], mu);
@@ -369,7 +379,6 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int d
         // the polynomial's first step: its companion row is untouched (the
         // identity steps of the levels above keep values), h[0][M-1-k] =
         // -b_k of the (scaled) monic polynomial
-        const bool first = here && its == 0 && d == M;
         if (__ballot(first)) {  // wave-uniform
             const cx<T> b0 = {-h[0][M - 1].re, -h[0][M - 1].im};
             const cx<T> b1 = {-h[0][M - 2].re, -h[0][M - 2].im};
@@ -382,10 +391,14 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int d
             mu = {pick(take, z.re, mu.re), pick(take, z.im, mu.im)};
         }
     }
-    const cx<T> sh = {pick(act, pick(ex, ere, mu.re), T(0)),
-                      pick(act, pick(ex, eim, mu.im), T(0))};
-    m = done ? M - 1 : m;
-    its = done ? 0 : its + (act ? 1 : 0);
+    // the exceptional shift (10th and 20th step of a level), computed in
+    // FP64 only when some lane of the wave takes it
+    if (__ballot(ex && act)) {  // wave-uniform
+        const T ere = (T)((double)h[M - 1][M - 1].re + hh * 0.75);
+        const T eim = (T)((double)h[M - 1][M - 1].im + hh * 0.5);
+        mu = {pick(ex, ere, mu.re), pick(ex, eim, mu.im)};
+    }
+    const cx<T> sh = {pick(act, mu.re, T(0)), pick(act, mu.im, T(0))};
     qr_step<T, DM, M>(h, sh, act);
 }
 
@@ -873,15 +886,97 @@ __global__ __launch_bounds__(kWave) void solve_tiled_kernel(PolyIO io, int tile)
     }
 }
 
+// Mixed degrees, one block (one wave) per (tile, slice): no loop around the
+// solve, so the kernel keeps the flat kernel's register allocation (FP32 96
+// VGPRs, 5 waves per SIMD; FP64 160-166, 3 waves) where the persistent tile
+// loop above costs 10-20 more (one wave per SIMD fewer).  Block b takes slot
+// `slot` of tile t: the tile's polynomials are bucketed by degree as above
+// (index order within a bucket, each bucket cut into slices of 64), and slot
+// s is the s-th slice in bucket order; a slot past the tile's slices exits at
+// once.  Blocks are dealt to the 8 XCDs round-robin, so consecutive blocks of
+// one XCD (b = xcd + 8 q) take the slots of one tile in turn: a tile's
+// slices run together on one XCD and share its L2, which holds the tile's
+// coefficients for all of them.
+template <bool FP32, int DM, int BIN>
+__global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile, int slots,
+                                                             int64_t ntiles)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t q = b >> 3;
+    const int slot = (int)(q % slots);
+    const int64_t t = (q / slots) * 8 + (b & 7);
+    if (t >= ntiles)
+        return;
+    const int64_t base = t * tile;
+    const int cnt_t = (int)((io.n - base) < tile ? (io.n - base) : tile);
+    const int lane = threadIdx.x;
+    auto bucket = [&](int64_t g) -> int {
+        const int d = io.degrees[g];
+        return (d >= 1 && d <= DM) ? d : 0;
+    };
+    // bucket sizes (bucket 0 = invalid degree), then the slot's bucket and
+    // the rank within it of the slice's first polynomial
+    int count[DM + 1];
+#pragma unroll
+    for (int k = 0; k <= DM; ++k)
+        count[k] = 0;
+    for (int t0 = 0; t0 < cnt_t; t0 += kWave) {
+        const int tt = t0 + lane;
+        const int bk = tt < cnt_t ? bucket(base + tt) : -1;
+#pragma unroll
+        for (int k = 0; k <= DM; ++k)
+            count[k] += __builtin_popcountll(__ballot(bk == k));
+    }
+    int mine = -1, r0 = 0, acc = 0;
+#pragma unroll
+    for (int k = 0; k <= DM; ++k) {
+        const int slices = (count[k] + kWave - 1) / kWave;
+        if (mine < 0 && slot < acc + slices) {
+            mine = k;
+            r0 = (slot - acc) * kWave;
+        }
+        acc += slices;
+    }
+    if (mine < 0)
+        return;
+    // the slice's tile-local indices, in index order
+    __shared__ uint16_t list[kWave];
+    list[lane] = 0xFFFF;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this lane
+    int rank = 0;
+    for (int t0 = 0; t0 < cnt_t && rank < r0 + kWave; t0 += kWave) {
+        const int tt = t0 + lane;
+        const int bk = tt < cnt_t ? bucket(base + tt) : -1;
+        const uint64_t m = __ballot(bk == mine);
+        const int r = rank + __builtin_popcountll(m & below);
+        if (bk == mine && r >= r0 && r < r0 + kWave)
+            list[r - r0] = (uint16_t)tt;
+        rank += __builtin_popcountll(m);
+    }
+    __syncthreads();
+    const uint16_t e = list[lane];
+    const bool valid = e != 0xFFFF;
+    solve_poly<FP32, DM, BIN>(io, base + (valid ? e : 0), valid);
+}
+
 template <bool FP32, int DM, int BIN>
 hipError_t launch_layout(const PolyIO& io, const SolveArgs& a, hipStream_t stream)
 {
     if (a.degrees && a.tile > 0) {
         const int tile = a.tile;
         const int64_t tiles = (a.n + tile - 1) / tile;
-        const int64_t grid = a.grid_blocks > 0 && a.grid_blocks < tiles ? a.grid_blocks : tiles;
-        hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM, BIN, false>), dim3((unsigned)grid),
-                           dim3(kWave), 0, stream, io, tile);
+        const int slots = (tile + kWave - 1) / kWave + DM;  // >= the slices of any tile
+        const int64_t sliced = (tiles + 7) / 8 * 8 * slots;
+        if (a.grid_blocks == 0 && sliced <= 0x7fffffff) {
+            hipLaunchKernelGGL((solve_sliced_kernel<FP32, DM, BIN>), dim3((unsigned)sliced),
+                               dim3(kWave), 0, stream, io, tile, slots, tiles);
+        } else {
+            const int64_t want = a.grid_blocks > 0 ? a.grid_blocks : a.fallback_grid;
+            const int64_t grid = want < tiles ? want : tiles;
+            hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM, BIN, false>), dim3((unsigned)grid),
+                               dim3(kWave), 0, stream, io, tile);
+        }
     } else {
         const int64_t blocks = (a.n + kBlock - 1) / kBlock;
         hipLaunchKernelGGL((solve_flat_kernel<FP32, DM, BIN>), dim3((unsigned)blocks),

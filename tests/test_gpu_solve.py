@@ -291,7 +291,9 @@ def test_tiled_equals_flat(precision):
     deg[::997] = 0          # invalid degrees mixed in
     deg[5::1009] = 7
     flat = _solve(a, deg, precision, tile=-1, iter_counts=True)
-    for tile, grid in [(64, 0), (100, 3), (2048, 0), (4096, 1), (1000, 7), (2048, 100000)]:
+    # grid 0: one wave per (tile, slice); > 0: persistent waves walking the tiles
+    for tile, grid in [(64, 0), (100, 0), (512, 0), (1000, 0), (4096, 0), (100, 3), (2048, 64),
+                       (4096, 1), (1000, 7), (2048, 100000)]:
         got = _solve(a, deg, precision, tile=tile, grid_blocks=grid, iter_counts=True)
         for x, y in zip(got, flat):
             assert np.array_equal(x, y, equal_nan=True), (tile, grid)
