@@ -547,6 +547,14 @@ __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs
 // (relative error about 2^-48) instead of a correctly rounded division.
 // last2 receives |last step|^2.
 constexpr int kPolishGroup = 2;  // 1, 3 and 6 measured no faster
+
+// x y + z for complex FP64 values as four fused multiply-adds (each part's
+// two products accumulated into z's part in one chain).
+__device__ __forceinline__ cx<double> mul_add(cx<double> x, cx<double> y, cx<double> z)
+{
+    return {__builtin_fma(x.re, y.re, __builtin_fma(-x.im, y.im, z.re)),
+            __builtin_fma(x.re, y.im, __builtin_fma(x.im, y.re, z.im))};
+}
 template <int DM, int K0, int G>
 __device__ __forceinline__ void polish_group(cx<double> (&r)[DM], const cx<double> (&a)[DM + 1],
                                              int steps, double (&last2)[DM])
@@ -565,8 +573,8 @@ __device__ __forceinline__ void polish_group(cx<double> (&r)[DM], const cx<doubl
         for (int k = DM - 1; k >= 0; --k)
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                dp[g] = dp[g] * r[K0 + g] + p[g];
-                p[g] = p[g] * r[K0 + g] + a[k];
+                dp[g] = mul_add(dp[g], r[K0 + g], p[g]);
+                p[g] = mul_add(p[g], r[K0 + g], a[k]);
             }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
