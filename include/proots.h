@@ -96,6 +96,11 @@ enum pr_solve_flags {
                                                and solves only those); its roots, status (with
                                                PR_ST_RESOLVED_FP64) and iteration counts are
                                                then the FP64 solve's.  No effect on PR_FP64 */
+    PR_FLAG_PAIRED_LANES = 1u << 4,         /* FP32 form, index-order launch (no tiles):
+                                               each lane solves two polynomials, 64 apart,
+                                               stepping both matrices in one level loop;
+                                               results identical to the one-per-lane launch.
+                                               Ignored by the FP64 form and tiled launches */
     PR_FLAG_RAYLEIGH_SHIFT = 1u << 3        /* shift each QR step by Alg. 1's choice, the
                                                bottom-right entry itself.  Default: the
                                                eigenvalue of the trailing 2 x 2 block nearest

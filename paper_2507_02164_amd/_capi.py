@@ -36,6 +36,7 @@ FLAG_NO_EXCEPTIONAL_SHIFT = 1 << 0
 FLAG_FIXED_STEPS = 1 << 1
 FLAG_FP64_FALLBACK = 1 << 2
 FLAG_RAYLEIGH_SHIFT = 1 << 3
+FLAG_PAIRED_LANES = 1 << 4
 
 
 class ProotsError(RuntimeError):
@@ -166,6 +167,8 @@ def _prepare_solve(coeffs, degrees, precision, max_iter_per_level, polish_steps,
             tile = tuned.get("tile", 0)
         if grid_blocks is None:
             grid_blocks = tuned.get("grid_blocks", 0)
+        if tuned.get("paired") and tile == -1:
+            flags |= FLAG_PAIRED_LANES
     opts = SolveOpts(prec, max_iter_per_level, polish_steps, flags, polish_tol,
                      None if its is None or its.numel() == 0 else its.data_ptr(), tile, grid_blocks)
     return dmax, n, roots, status, its, opts

@@ -8,6 +8,8 @@ the GPU (HIP events, median of repeats) and keeps the fastest:
                     slice of 64 same-degree polynomials), or the number of
                     persistent one-wave blocks walking the tiles (tried at
                     several per compute unit),
+  * paired       -- FP32 form, index order: one or two polynomials per lane
+                    (PR_FLAG_PAIRED_LANES),
   * cap          -- QR steps per level before NOT_CONVERGED; a cap is only
                     eligible if it flags no polynomial of the sample that the
                     default cap of 30 does not flag, and a smaller cap is only
@@ -108,8 +110,9 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
     roots = torch.empty((dmax, n), dtype=torch.complex128, device=dev)
     status = torch.empty((n,), dtype=torch.int32, device=dev)
 
-    def run(**o):
-        _capi.solve(coeffs, degrees, precision, roots=roots, status=status, **o)
+    def run(paired=0, **o):
+        flags = _capi.FLAG_PAIRED_LANES if paired else 0
+        _capi.solve(coeffs, degrees, precision, roots=roots, status=status, flags=flags, **o)
 
     # caps that flag nothing extra
     run(max_iter_per_level=30, tile=-1)
@@ -122,6 +125,8 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
         if int(((status & _capi.ST_NOT_CONVERGED) != 0).sum()) <= base_flags:
             caps.append(cap)
     layouts = [dict(tile=-1)]
+    if precision == "fp32_polish":
+        layouts.append(dict(tile=-1, paired=1))   # two polynomials per lane
     if degrees is not None:
         layouts += [dict(tile=t, grid_blocks=0) for t in SLICED_TILES]
         layouts += [dict(tile=t, grid_blocks=b * cus) for t in TILES for b in BLOCKS_PER_CU]

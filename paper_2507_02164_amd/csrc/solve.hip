@@ -807,6 +807,186 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
     }
 }
 
+// Two polynomials per lane (FP32 form, index order; PR_FLAG_PAIRED_LANES):
+// lane l of block b solves polynomials 128 b + l and 128 b + 64 + l, their two
+// matrices stepped in the same level loop -- two independent instruction
+// streams per wave, at twice the registers per lane.  Same arithmetic per
+// polynomial as the one-per-lane kernel.
+template <int DM, int M, typename E0, typename E1>
+__device__ __forceinline__ void iterate_pair_from(cx<float> (&h0)[DM][DM], cx<float> (&h1)[DM][DM],
+                                                  int (&m)[2], int (&its)[2], const int (&d)[2],
+                                                  int cap, bool exc, bool fixed, bool wilk,
+                                                  uint32_t (&st)[2], int32_t* __restrict__ iters,
+                                                  int64_t n, const int64_t (&i)[2], E0&& emit0,
+                                                  E1&& emit1)
+{
+    if constexpr (M >= 2) {
+        while (__ballot(m[0] == M || m[1] == M)) {
+            trip<float, DM, M>(h0, m[0], its[0], d[0], cap, exc, fixed, wilk, st[0], iters, n,
+                               i[0], emit0);
+            trip<float, DM, M>(h1, m[1], its[1], d[1], cap, exc, fixed, wilk, st[1], iters, n,
+                               i[1], emit1);
+            if (!__ballot(m[0] == M || m[1] == M))
+                break;
+            trip<float, DM, M>(h0, m[0], its[0], d[0], cap, exc, fixed, wilk, st[0], iters, n,
+                               i[0], emit0);
+            trip<float, DM, M>(h1, m[1], its[1], d[1], cap, exc, fixed, wilk, st[1], iters, n,
+                               i[1], emit1);
+        }
+        iterate_pair_from<DM, M - 1>(h0, h1, m, its, d, cap, exc, fixed, wilk, st, iters, n, i,
+                                     emit0, emit1);
+    }
+}
+
+template <int DM, int BIN>
+__device__ __forceinline__ void solve_pair(const PolyIO& io, const int64_t (&i)[2],
+                                           const bool (&valid)[2])
+{
+    const int64_t n = io.n;
+    const bool store = BIN != kBinKeep || io.roots != nullptr;  // wave-uniform
+    const double qnan = __builtin_nan("");
+    const bool fixed = (io.flags & PR_FLAG_FIXED_STEPS) != 0;
+    const bool exc = !(io.flags & PR_FLAG_NO_EXCEPTIONAL_SHIFT) && !fixed;
+    const bool wilk = !(io.flags & PR_FLAG_RAYLEIGH_SHIFT) && !fixed;
+    int d[2], dd[2], sc[2], m[2], its[2];
+    uint32_t st[2];
+    bool ok[2];
+    cx<float> h[2][DM][DM];
+    cx<float> e[2][DM];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        d[p] = valid[p] ? (io.degrees ? io.degrees[i[p]] : DM) : 0;
+        st[p] = 0;
+        if (valid[p] && (d[p] < 1 || d[p] > DM))
+            st[p] = PR_ST_BAD_DEGREE;
+        cx<double> a[DM + 1], b[DM + 1];
+#pragma unroll
+        for (int k = 0; k <= DM; ++k)
+            a[k] = b[k] = {0.0, 0.0};
+        if (valid[p] && !st[p])
+            st[p] = load_poly<DM>(io.coeffs, n, i[p], d[p], a, b);
+        ok[p] = valid[p] && !st[p];
+        dd[p] = ok[p] ? d[p] : 0;
+        if (valid[p]) {
+            if (store)
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k >= dd[p])
+                        io.roots[(int64_t)k * n + i[p]] = make_double2(qnan, qnan);
+            if (io.iters)
+#pragma unroll
+                for (int mm = 2; mm <= DM; ++mm)
+                    if (mm > dd[p])
+                        io.iters[(int64_t)(mm - 2) * n + i[p]] = 0;
+        }
+#pragma unroll
+        for (int r = 0; r < DM; ++r)
+#pragma unroll
+            for (int c = (r > 0 ? r - 1 : 0); c < DM; ++c)
+                h[p][r][c] = {0.0f, 0.0f};
+        sc[p] = ok[p] ? root_scale<float, DM>(b, d[p]) : 0;
+        companion<float, DM>(h[p], dd[p], b, sc[p]);
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            e[p][k] = {0.0f, 0.0f};
+        m[p] = dd[p];
+        its[p] = 0;
+    }
+    auto emit0 = [&](int k, cx<float> v) {
+#pragma unroll
+        for (int q = 0; q < DM; ++q)
+            if (q == k)
+                e[0][q] = v;
+    };
+    auto emit1 = [&](int k, cx<float> v) {
+#pragma unroll
+        for (int q = 0; q < DM; ++q)
+            if (q == k)
+                e[1][q] = v;
+    };
+    iterate_pair_from<DM, DM>(h[0], h[1], m, its, dd, io.cap, exc, fixed, wilk, st, io.iters, n,
+                              i, emit0, emit1);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        int bins[DM];
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            bins[k] = -1;
+        e[p][0] = h[p][0][0];
+        if (ok[p]) {
+            cx<double> a[DM + 1];
+#pragma unroll
+            for (int k = 0; k <= DM; ++k) {
+                a[k] = {0.0, 0.0};
+                if (k <= d[p]) {
+                    const double2 v = load_stream(io.coeffs_again + (int64_t)k * n + i[p]);
+                    const int ex = sc[p] * (k - d[p]);
+                    a[k] = {__builtin_ldexp(v.x, ex), __builtin_ldexp(v.y, ex)};
+                }
+            }
+            cx<double> r[DM];
+            double last2[DM];
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                r[k] = {(double)e[p][k].re, (double)e[p][k].im};
+            polish_all<DM, 0>(r, a, io.polish_steps, last2, d[p]);
+            const double tol2 = io.polish_tol * io.polish_tol;
+            bool bad = false;
+#pragma unroll
+            for (int k = 0; k < DM; ++k) {
+                if (k < d[p]) {
+                    if (!(last2[k] <= tol2 * norm2(r[k])))
+                        bad = true;
+                } else {
+                    r[k] = {qnan, qnan};
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < DM; ++j)
+#pragma unroll
+                for (int k = j + 1; k < DM; ++k)
+                    if (k < d[p]) {
+                        double sep2 = norm2(r[j] - r[k]);
+                        double mag = fmax(norm2(r[j]), 1.0) * 1e-16;
+                        if (sep2 <= mag)
+                            bad = true;
+                    }
+            if (bad)
+                st[p] |= PR_ST_POLISH_UNCONVERGED;
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                r[k] = {__builtin_ldexp(r[k].re, sc[p]), __builtin_ldexp(r[k].im, sc[p])};
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                if (k < d[p]) {
+                    if (store)
+                        store_stream(io.roots + (int64_t)k * n + i[p],
+                                     make_double2(r[k].re, r[k].im));
+                    if constexpr (BIN != kBinNone)
+                        bins[k] = pixel_of(r[k].re, r[k].im, io.win);
+                }
+        }
+        st[p] |= io.status_or;
+        if (valid[p])
+            io.status[i[p]] = st[p];
+        if constexpr (BIN != kBinNone) {
+            const bool keep = valid[p] && !(st[p] & (io.skip_mask | io.defer_mask));
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                wave_count(keep ? bins[k] : -1, io.win.hist);
+        }
+    }
+}
+
+template <int DM, int BIN>
+__global__ __launch_bounds__(kBlock) void solve_pair_kernel(PolyIO io)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * (2 * kBlock) + threadIdx.x;
+    const int64_t i[2] = {i0, i0 + kBlock};
+    const bool valid[2] = {i[0] < io.n, i[1] < io.n};
+    solve_pair<DM, BIN>(io, i, valid);
+}
+
 // No occupancy hints: the register allocation as it comes (FP32 96 VGPRs, 5
 // waves per SIMD; FP64 158, 3 waves) measured faster than any forced
 // occupancy, which spills.
@@ -985,6 +1165,10 @@ hipError_t launch_layout(const PolyIO& io, const SolveArgs& a, hipStream_t strea
             hipLaunchKernelGGL((solve_tiled_kernel<FP32, DM, BIN, false>), dim3((unsigned)grid),
                                dim3(kWave), 0, stream, io, tile);
         }
+    } else if (FP32 && BIN != kBinReread && (a.flags & PR_FLAG_PAIRED_LANES)) {
+        const int64_t blocks = (a.n + 2 * kBlock - 1) / (2 * kBlock);
+        hipLaunchKernelGGL((solve_pair_kernel<DM, BIN == kBinReread ? kBinNone : BIN>),
+                           dim3((unsigned)blocks), dim3(kBlock), 0, stream, io);
     } else {
         const int64_t blocks = (a.n + kBlock - 1) / kBlock;
         hipLaunchKernelGGL((solve_flat_kernel<FP32, DM, BIN>), dim3((unsigned)blocks),

@@ -103,7 +103,7 @@ def test_solve_argument_validation(lib):
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_INVALID_ARG
     bad = pr.SolveOpts(flags=0x80)
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
-    bad = pr.SolveOpts(flags=0x10)
+    bad = pr.SolveOpts(flags=0x20)
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
     fb = pr.SolveOpts(precision=pr.FP32_POLISH, flags=pr.FLAG_FP64_FALLBACK | pr.FLAG_FIXED_STEPS |
                       pr.FLAG_RAYLEIGH_SHIFT)

@@ -301,6 +301,37 @@ def test_tiled_equals_flat(precision):
     np.testing.assert_array_equal(flat[1].astype(np.uint32) & 0x7, ref_st & 0x7)
 
 
+@pytest.mark.parametrize("n", [1, 64, 127, 128, 129, 5000, 65536])
+def test_paired_lanes_match_the_oracle(n):
+    """PR_FLAG_PAIRED_LANES packs two polynomials into each lane.  Each
+    polynomial's arithmetic is the same, but the compiler fuses multiply-adds
+    differently in the two kernels, so the roots are held to the oracle's
+    bounds (not to the one-per-lane kernel's bits); status and the one-launch
+    image follow the oracle's rules on the kernel's own roots, for ragged
+    batches and smaller dmax too."""
+    a = workloads.gaussian(n, seed=40 + n)
+    ref, ref_st = oracle.solve(a, flags=OW)
+    got, st, it = _solve(a, None, "fp32_polish", iter_counts=True, flags=pr.FLAG_PAIRED_LANES)
+    _, st1, it1 = _solve(a, None, "fp32_polish", iter_counts=True)
+    assert np.all((st & ~pr.ST_POLISH_UNCONVERGED) == 0)
+    _check_roots(got, st, a, None, ref, ref_st, flagged_ok=True)
+    assert (it == it1).mean() > 0.95
+    win, shape = workloads.GAUSSIAN_WINDOW, (256, 256)
+    ad = to_dev(a)
+    r2, s2, h2 = pr.solve_bin(ad, win, shape, None, "fp32_polish", flags=pr.FLAG_PAIRED_LANES)
+    torch.cuda.synchronize()
+    want = oracle.density(to_host(r2), win, shape, None, to_host(s2).astype(np.uint32), 0)
+    assert np.array_equal(to_host(h2), want)
+    rng = np.random.default_rng(n)
+    b = (rng.standard_normal((5, n)) + 1j * rng.standard_normal((5, n))) / np.sqrt(2)
+    deg = rng.integers(0, 6, n).astype(np.int32)          # 0 and 5 (> dmax 4): invalid
+    deg[0] = 4
+    ref, ref_st = oracle.solve(b, deg, flags=OW)
+    got, st = _solve(b, deg, "fp32_polish", tile=-1, flags=pr.FLAG_PAIRED_LANES)
+    assert np.array_equal(st & 0x7, ref_st & 0x7)
+    _check_roots(got, st, b, deg, ref, ref_st, floor=1e-9, flagged_ok=True)
+
+
 def test_tile_argument_validation():
     a = to_dev(workloads.gaussian(16, seed=0))
     d = to_dev(np.full(16, 6, dtype=np.int32))
