@@ -329,7 +329,8 @@ def config_legs(args, torch, workloads, pr, dev):
         return d
 
     # C1: 65,536 Gaussian degree-6 polynomials, FP64 (the configuration's
-    # form) and FP32 + polish, solve + 256 x 256 image in one launch
+    # form) and FP32 + polish, solve + 256 x 256 image in one launch; each
+    # also with lanes running one level ahead ("run_ahead")
     log("C1: gaussian 65,536, 256x256 image")
     n = 65536
     a = torch.from_numpy(workloads.gaussian(n, 0)).to(dev)
@@ -345,6 +346,12 @@ def config_legs(args, torch, workloads, pr, dev):
         ms = _median_ms(torch, lambda: (h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r,
                                                                  status=s, out=h)), reps, warm)
         c1[form] = leg(n, ms, fl, PEAK_FP64 if form == "fp64" else PEAK_FP32, **flagged(s))
+        ms = _median_ms(torch, lambda: (h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r,
+                                                                 status=s, out=h,
+                                                                 flags=pr.FLAG_RUN_AHEAD)),
+                        reps, warm)
+        c1[form]["run_ahead"] = leg(n, ms, fl, PEAK_FP64 if form == "fp64" else PEAK_FP32,
+                                    **flagged(s))
     out["c1_gaussian65536"] = c1
     del a, r, s, h
 
@@ -406,7 +413,7 @@ def config_legs(args, torch, workloads, pr, dev):
     del a, cot, r, s, gc, coeffs
 
     # C5: 16 Mi polynomials with a triple root cluster, both forms, solve +
-    # 1920 x 1080 image in one launch
+    # 1920 x 1080 image in one launch, lock-step and run-ahead
     n = 16 * 2 ** 20
     log("C5: generating 16Mi clustered polynomials")
     a = torch.from_numpy(workloads.clustered(n, 0)[0]).to(dev)
@@ -424,6 +431,12 @@ def config_legs(args, torch, workloads, pr, dev):
         ms = _median_ms(torch, lambda: (h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r,
                                                                  status=s, out=h)), reps, warm)
         c5[form] = leg(n, ms, fl, PEAK_FP64 if form == "fp64" else PEAK_FP32, **flagged(s))
+        ms = _median_ms(torch, lambda: (h.zero_(), pr.solve_bin(a, win, shape, None, form, roots=r,
+                                                                 status=s, out=h,
+                                                                 flags=pr.FLAG_RUN_AHEAD)),
+                        reps, warm)
+        c5[form]["run_ahead"] = leg(n, ms, fl, PEAK_FP64 if form == "fp64" else PEAK_FP32,
+                                    **flagged(s))
     out["c5_clustered16Mi"] = c5
     del a, r, s, h
     torch.cuda.empty_cache()

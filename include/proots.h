@@ -99,8 +99,23 @@ enum pr_solve_flags {
     PR_FLAG_PAIRED_LANES = 1u << 4,         /* FP32 form, index-order launch (no tiles):
                                                each lane solves two polynomials, 64 apart,
                                                stepping both matrices in one level loop;
-                                               results identical to the one-per-lane launch.
-                                               Ignored by the FP64 form and tiled launches */
+                                               the same arithmetic per polynomial as the
+                                               one-per-lane launch (roots may differ in the
+                                               last bits where the compiler fuses products
+                                               differently).  Ignored by the FP64 form and
+                                               tiled launches */
+    PR_FLAG_RUN_AHEAD = 1u << 5,            /* one-per-lane launches (index order, and the
+                                               sliced mixed-degree layout, grid_blocks 0):
+                                               while a wave still steps level m for some
+                                               lanes, the lanes already at level m - 1 take
+                                               their level-(m-1) steps inside the same trips
+                                               instead of idling (Sec. III's next-task
+                                               scheduling, one level deep).  Same tests,
+                                               shifts and steps per lane as without it, so
+                                               roots, status and step counts agree up to
+                                               rounding.  Ignored by the persistent tiled
+                                               layout (grid_blocks > 0), by paired lanes
+                                               and by the FP64 fallback's second launch */
     PR_FLAG_RAYLEIGH_SHIFT = 1u << 3        /* shift each QR step by Alg. 1's choice, the
                                                bottom-right entry itself.  Default: the
                                                eigenvalue of the trailing 2 x 2 block nearest

@@ -37,6 +37,7 @@ FLAG_FIXED_STEPS = 1 << 1
 FLAG_FP64_FALLBACK = 1 << 2
 FLAG_RAYLEIGH_SHIFT = 1 << 3
 FLAG_PAIRED_LANES = 1 << 4
+FLAG_RUN_AHEAD = 1 << 5
 
 
 class ProotsError(RuntimeError):
@@ -163,12 +164,17 @@ def _prepare_solve(coeffs, degrees, precision, max_iter_per_level, polish_steps,
         tuned = autotune.tuned_options(name, dmax, degrees is not None, dev)
         if max_iter_per_level is None:
             max_iter_per_level = tuned.get("max_iter_per_level", 0)
+        # the tuned layout (tile, and its flags) only when the caller left
+        # the layout to the tuner
+        layout_tuned = tile is None
         if tile is None:
             tile = tuned.get("tile", 0)
         if grid_blocks is None:
             grid_blocks = tuned.get("grid_blocks", 0)
-        if tuned.get("paired") and tile == -1:
+        if layout_tuned and tuned.get("paired") and tile == -1:
             flags |= FLAG_PAIRED_LANES
+        if layout_tuned and tuned.get("ahead") and (tile == -1 or (tile > 0 and grid_blocks == 0)):
+            flags |= FLAG_RUN_AHEAD
     opts = SolveOpts(prec, max_iter_per_level, polish_steps, flags, polish_tol,
                      None if its is None or its.numel() == 0 else its.data_ptr(), tile, grid_blocks)
     return dmax, n, roots, status, its, opts

@@ -10,6 +10,8 @@ the GPU (HIP events, median of repeats) and keeps the fastest:
                     several per compute unit),
   * paired       -- FP32 form, index order: one or two polynomials per lane
                     (PR_FLAG_PAIRED_LANES),
+  * ahead        -- one-per-lane launches: lock-step levels, or lanes one
+                    level below the wave's running ahead (PR_FLAG_RUN_AHEAD),
   * cap          -- QR steps per level before NOT_CONVERGED; a cap is only
                     eligible if it flags no polynomial of the sample that the
                     default cap of 30 does not flag, and a smaller cap is only
@@ -110,8 +112,8 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
     roots = torch.empty((dmax, n), dtype=torch.complex128, device=dev)
     status = torch.empty((n,), dtype=torch.int32, device=dev)
 
-    def run(paired=0, **o):
-        flags = _capi.FLAG_PAIRED_LANES if paired else 0
+    def run(paired=0, ahead=0, **o):
+        flags = (_capi.FLAG_PAIRED_LANES if paired else 0) | (_capi.FLAG_RUN_AHEAD if ahead else 0)
         _capi.solve(coeffs, degrees, precision, roots=roots, status=status, flags=flags, **o)
 
     # caps that flag nothing extra
@@ -124,11 +126,11 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
         torch.cuda.synchronize()
         if int(((status & _capi.ST_NOT_CONVERGED) != 0).sum()) <= base_flags:
             caps.append(cap)
-    layouts = [dict(tile=-1)]
+    layouts = [dict(tile=-1), dict(tile=-1, ahead=1)]
     if precision == "fp32_polish":
         layouts.append(dict(tile=-1, paired=1))   # two polynomials per lane
     if degrees is not None:
-        layouts += [dict(tile=t, grid_blocks=0) for t in SLICED_TILES]
+        layouts += [dict(tile=t, grid_blocks=0, ahead=a) for t in SLICED_TILES for a in (0, 1)]
         layouts += [dict(tile=t, grid_blocks=b * cus) for t in TILES for b in BLOCKS_PER_CU]
     trials = []
     for cap in caps:

@@ -189,17 +189,33 @@ __device__ __forceinline__ void rot_cols_zero_real(cx<T>& x, cx<T>& y, cx<T> c, 
 // lane-divergent branch around it, matters: a divergent branch would keep
 // the pre-step matrix of the lanes that skip it alive next to the post-step
 // matrix of the lanes that take it, doubling the register footprint.
-template <typename T, int DM, int M>
-__device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
+//
+// AHEAD (run-ahead level loop): lanes with act && !act_last are one level
+// below, M-1, and take the step of their leading (M-1) x (M-1) block inside
+// this one.  Their last rotation (rows M-2, M-1) is the identity, and row and
+// column M-1, which hold the root they have already emitted and its
+// coupling, keep their values: the shift is neither taken from nor given
+// back to h[M-1][M-1], and h[M-2][M-2], whose last update is then column
+// rotation M-2, gets its shift back there.  The leading block goes through
+// the same operations as in the level-(M-1) step; the entries of column M-1
+// above it are rotated too, which changes nothing the lane still needs.
+template <typename T, int DM, int M, bool AHEAD = false>
+__device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act, bool act_last)
 {
     // the shortened rotation of the annihilated row, inside the loop and at
     // its end; inside the loop in FP64 it measured 170 VGPRs instead of 160
     // (one wave per SIMD fewer), so FP64 takes the plain rotation there
     constexpr bool kZeroInLoop = std::is_same<T, float>::value;
+    // shift of the bottom row (lanes at level M) and of the run-ahead lanes'
+    // bottom row M-2 at its last update
+    const cx<T> shl = AHEAD ? cx<T>{pick(act_last, sh.re, T(0)), pick(act_last, sh.im, T(0))} : sh;
+    const cx<T> shb = AHEAD ? cx<T>{pick(act_last, T(0), sh.re), pick(act_last, T(0), sh.im)}
+                            : cx<T>{T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        h[i][i].re -= sh.re;
-        h[i][i].im -= sh.im;
+        const cx<T> si = (i == M - 1) ? shl : sh;
+        h[i][i].re -= si.re;
+        h[i][i].im -= si.im;
     }
     cx<T> cprev, sprev;
     bool goprev = false;
@@ -211,7 +227,7 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
         // a lane rotates only if it acts this trip and (a, b) is not
         // (numerically) zero -- NaN fails the test too; otherwise
         // (c, s) = (1, 0) and both entries stay
-        const bool go = act && rotates(n2);
+        const bool go = (r == M - 1 ? act_last : act) && rotates(n2);
         // masking by arithmetic, two selects in all: a rotating lane takes
         // 1/rho and 0, a lane that keeps its entries 0 and 1, so that
         // c = conj(a)/rho or 1, s = conj(b)/rho or 0, and the rotation maps
@@ -230,14 +246,20 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
         if (r >= 2) {
             // lagged column rotation r-1 on rows 0..r-1 (row r-1 enters with
             // h[r-1][r-2] == 0 for lanes that took row rotation r-1)
+            // AHEAD, last one: row M-2's diagonal entry is complex for the
+            // run-ahead lanes (their row rotation M-1 was the identity) and
+            // takes its last update here, with their shift
+            const bool kAheadLast = AHEAD && r == M - 1;
 #pragma unroll
-            for (int j = 0; j < (kZeroInLoop ? r - 1 : r); ++j) {
+            for (int j = 0; j < (kZeroInLoop || kAheadLast ? r - 1 : r); ++j) {
                 if (j == r - 2)  // h[r-2][r-2] takes its last update: add the shift back
                     rot_cols_diag(h[j][r - 2], h[j][r - 1], cprev, sprev, sh);
                 else
                     rot_cols(h[j][r - 2], h[j][r - 1], cprev, sprev);
             }
-            if (kZeroInLoop)
+            if (kAheadLast)
+                rot_cols_zero(h[r - 1][r - 2], h[r - 1][r - 1], cprev, sprev, goprev, shb);
+            else if (kZeroInLoop)
                 rot_cols_zero_real(h[r - 1][r - 2], h[r - 1][r - 1], cprev, sprev, goprev);
         }
         cprev = c;
@@ -247,8 +269,8 @@ __device__ __forceinline__ void qr_step(cx<T> (&h)[DM][DM], cx<T> sh, bool act)
 #pragma unroll
     for (int j = 0; j < M - 2; ++j)
         rot_cols(h[j][M - 2], h[j][M - 1], cprev, sprev);
-    rot_cols_diag(h[M - 2][M - 2], h[M - 2][M - 1], cprev, sprev, sh);
-    rot_cols_zero(h[M - 1][M - 2], h[M - 1][M - 1], cprev, sprev, goprev, sh);
+    rot_cols_diag(h[M - 2][M - 2], h[M - 2][M - 1], cprev, sprev, shl);
+    rot_cols_zero(h[M - 1][M - 2], h[M - 1][M - 1], cprev, sprev, goprev, shl);
     // every diagonal entry got the shift back in its last update above
 }
 
@@ -399,46 +421,152 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int d
         mu = {pick(ex, ere, mu.re), pick(ex, eim, mu.im)};
     }
     const cx<T> sh = {pick(act, mu.re, T(0)), pick(act, mu.im, T(0))};
-    qr_step<T, DM, M>(h, sh, act);
+    qr_step<T, DM, M>(h, sh, act, act);
+}
+
+// A trip with run-ahead lanes (M >= 4).  As `trip` for the lanes at level
+// M; the lanes at level L = M-1 -- those already there and those that have
+// just deflated in this trip -- are not idle: they take the deflation test
+// and the shifted step of level L, on their leading block (see qr_step).  A
+// lane that deflated early thus gets on with its next level while the
+// wave's slower lanes finish this one.  Each lane takes exactly the tests,
+// shifts and steps it takes in lock-step, in the same order; only the trip
+// it takes them in changes.  (Levels 3 and 2 keep lock-step trips: their
+// steps are cheap enough that the second test and the selects below would
+// cost more than their idle lanes.)
+template <typename T, int DM, int M, typename Emit>
+__device__ __forceinline__ void trip_ahead(cx<T> (&h)[DM][DM], int& m, int& its, int d, int cap,
+                                           bool exc, bool fixed, bool wilk, uint32_t& st,
+                                           int32_t* __restrict__ iters, int64_t n, int64_t i,
+                                           Emit&& emit)
+{
+    static_assert(M >= 4, "run-ahead trips are taken from level 4 up");
+    constexpr int L = M - 1;
+    const bool here = m == M;
+    const double hh = cabs1_d(h[M - 1][M - 2]);
+    const double tt = cabs1_d(h[M - 1][M - 1]) + cabs1_d(h[M - 2][M - 2]);
+    // fixed-step mode (Alg. 2): no test, exactly `cap` steps per level
+    const bool conv = !fixed && hh <= Eps<T>::v * tt;
+    const bool done = here && (conv || its == cap);
+    if (done) {
+        if (!conv && !fixed)
+            st |= PR_ST_NOT_CONVERGED;
+        if (iters)
+            iters[(int64_t)(M - 2) * n + i] = its;
+        emit(M - 1, h[M - 1][M - 1]);
+    }
+    // the lanes at level L and their test there (itb: their steps at L)
+    const bool below = m == L || done;
+    const int itb = done ? 0 : its;
+    const double hhb = cabs1_d(h[L - 1][L - 2]);
+    const double ttb = cabs1_d(h[L - 1][L - 1]) + cabs1_d(h[L - 2][L - 2]);
+    const bool convb = !fixed && hhb <= Eps<T>::v * ttb;
+    const bool done_b = below && (convb || itb == cap);
+    if (done_b) {
+        if (!convb && !fixed)
+            st |= PR_ST_NOT_CONVERGED;
+        if (iters)
+            iters[(int64_t)(L - 2) * n + i] = itb;
+        emit(L - 1, h[L - 1][L - 1]);
+    }
+    const bool act = here && !done;
+    const bool act_b = below && !done_b;
+    const bool stp = act || act_b;
+    const int its_s = act_b ? itb : its;  // steps taken so far at the level stepped
+    const bool ex = exc && (its_s == 10 || its_s == 20);
+    const bool first = its_s == 0 && ((act && d == M) || (act_b && d == L));
+    m = done_b ? L - 1 : (done ? M - 1 : m);
+    its = done_b ? 0 : (stp ? its_s + 1 : (done ? 0 : its));
+    if (!__ballot(stp))
+        return;
+    // the trailing 2 x 2 block [[p, q], [c, e]] of the level the lane steps
+    const cx<T> p = {pick(act_b, h[L - 2][L - 2].re, h[M - 2][M - 2].re),
+                     pick(act_b, h[L - 2][L - 2].im, h[M - 2][M - 2].im)};
+    const cx<T> q = {pick(act_b, h[L - 2][L - 1].re, h[M - 2][M - 1].re),
+                     pick(act_b, h[L - 2][L - 1].im, h[M - 2][M - 1].im)};
+    const cx<T> c = {pick(act_b, h[L - 1][L - 2].re, h[M - 1][M - 2].re),
+                     pick(act_b, h[L - 1][L - 2].im, h[M - 1][M - 2].im)};
+    const cx<T> e = {pick(act_b, h[L - 1][L - 1].re, h[M - 1][M - 1].re),
+                     pick(act_b, h[L - 1][L - 1].im, h[M - 1][M - 1].im)};
+    cx<T> mu = e;
+    if (wilk) {  // wave-uniform: a scalar branch
+        const cx<T> w = wilkinson(p, q, c, mu);
+        const bool fin = __builtin_isfinite(w.re) && __builtin_isfinite(w.im);
+        mu = {pick(fin, w.re, mu.re), pick(fin, w.im, mu.im)};
+        // the polynomial's first step (see trip), at the level stepped: the
+        // companion row of degree k holds h[0][k-1-j] = -b_j
+        if (__ballot(first)) {  // wave-uniform
+            const cx<T> b0 = {pick(act_b, -h[0][L - 1].re, -h[0][M - 1].re),
+                              pick(act_b, -h[0][L - 1].im, -h[0][M - 1].im)};
+            const cx<T> b1 = {pick(act_b, -h[0][L - 2].re, -h[0][M - 2].re),
+                              pick(act_b, -h[0][L - 2].im, -h[0][M - 2].im)};
+            const cx<T> b2 = {pick(act_b, -h[0][L - 3].re, -h[0][M - 3].re),
+                              pick(act_b, -h[0][L - 3].im, -h[0][M - 3].im)};
+            bool ok;
+            const cx<T> z = quad_start(b0, b1, b2, ok);
+            const bool take = first && ok;
+            mu = {pick(take, z.re, mu.re), pick(take, z.im, mu.im)};
+        }
+    }
+    // the exceptional shift (10th and 20th step of a level)
+    if (__ballot(ex && stp)) {  // wave-uniform
+        const double hx = act_b ? hhb : hh;
+        const T ere = (T)((double)e.re + hx * 0.75);
+        const T eim = (T)((double)e.im + hx * 0.5);
+        mu = {pick(ex, ere, mu.re), pick(ex, eim, mu.im)};
+    }
+    const cx<T> sh = {pick(stp, mu.re, T(0)), pick(stp, mu.im, T(0))};
+    qr_step<T, DM, M, true>(h, sh, stp, act);
 }
 
 // Alg. 1's level loop for a wave of independent lanes, level by level: the
 // wave keeps taking trips at level M while any of its lanes is still at
 // level M (a wave-uniform condition), then moves on to M-1.  Lanes that
-// deflate early, or whose degree is below M, ride along with the identity.
-// Keeping the wave level-synchronous wastes less work on lane divergence
-// than letting every lane run its own level (a trip would then execute the
-// union of the levels present), and a separate loop per level lets each
-// loop carry only its own M x M block in registers.  The loop body holds two
-// trips (with the wave-uniform exit test between them): a one-trip body ends
-// with the rotated entries in other registers than it started with, and the
-// copies back at the loop edge cost both instructions and, above all,
-// registers; over two trips the register assignment closes up.
-template <typename T, int DM, int M, typename Emit>
+// deflate early, or whose degree is below M, ride along with the identity --
+// or, with AHEAD, run one level ahead (see trip_ahead).  Keeping the wave
+// level-synchronous wastes less work on lane divergence than letting every
+// lane run its own level (a trip would then execute the union of the levels
+// present), and a separate loop per level lets each loop carry only its own
+// M x M block in registers.  The loop body holds two trips (with the
+// wave-uniform exit test between them): a one-trip body ends with the
+// rotated entries in other registers than it started with, and the copies
+// back at the loop edge cost both instructions and, above all, registers;
+// over two trips the register assignment closes up.
+template <typename T, int DM, int M, bool AHEAD, typename Emit>
 __device__ __forceinline__ void iterate_from(cx<T> (&h)[DM][DM], int& m, int& its, int d, int cap,
                                              bool exc, bool fixed, bool wilk, uint32_t& st,
                                              int32_t* __restrict__ iters, int64_t n, int64_t i,
                                              Emit&& emit)
 {
     if constexpr (M >= 2) {
-        while (__ballot(m == M)) {
-            trip<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
-            if (!__ballot(m == M))
-                break;
-            trip<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
+        if constexpr (AHEAD && M >= 4) {
+            while (__ballot(m == M)) {
+                trip_ahead<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
+                if (!__ballot(m == M))
+                    break;
+                trip_ahead<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
+            }
+        } else {
+            while (__ballot(m == M)) {
+                trip<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
+                if (!__ballot(m == M))
+                    break;
+                trip<T, DM, M>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
+            }
         }
-        iterate_from<T, DM, M - 1>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
+        iterate_from<T, DM, M - 1, AHEAD>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i,
+                                          emit);
     }
 }
 
-template <typename T, int DM, typename Emit>
+template <typename T, int DM, bool AHEAD, typename Emit>
 __device__ __forceinline__ void iterate(cx<T> (&h)[DM][DM], int d, int cap, bool exc,
                                         bool fixed, bool wilk, uint32_t& st,
                                         int32_t* __restrict__ iters, int64_t n, int64_t i,
                                         Emit&& emit)
 {
     int m = d, its = 0;
-    iterate_from<T, DM, DM>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
+    iterate_from<T, DM, DM, AHEAD>(h, m, its, d, cap, exc, fixed, wilk, st, iters, n, i, emit);
 }
 
 // Companion matrix, first-row form: h[0][j] = -b_{d-1-j} for j < d, ones on
@@ -644,7 +772,7 @@ constexpr uint32_t kFallbackBits = PR_ST_NOT_CONVERGED | PR_ST_POLISH_UNCONVERGE
 // FP32 selects the FP32-sweep + FP64-polish form; BIN != kBinNone adds the
 // binning epilogue (kBinKeep lets io.roots be null).  No early return: every
 // lane of the wave reaches the wave-uniform loops and the epilogue's ballots.
-template <bool FP32, int DM, int BIN>
+template <bool FP32, int DM, int BIN, bool AHEAD = false>
 __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool valid)
 {
     using T = typename std::conditional<FP32, float, double>::type;
@@ -692,7 +820,7 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
     const bool wilk = !(io.flags & PR_FLAG_RAYLEIGH_SHIFT) && !fixed;
 
     if constexpr (!FP32) {
-        iterate<double, DM>(h, dd, io.cap, exc, fixed, wilk, st, io.iters, n, i, [&](int k, cx<double> w) {
+        iterate<double, DM, AHEAD>(h, dd, io.cap, exc, fixed, wilk, st, io.iters, n, i, [&](int k, cx<double> w) {
             const cx<double> v = {__builtin_ldexp(w.re, sc), __builtin_ldexp(w.im, sc)};
             if (store)
                 io.roots[(int64_t)k * n + i] = make_double2(v.re, v.im);
@@ -726,7 +854,7 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
 #pragma unroll
         for (int k = 0; k < DM; ++k)
             e[k] = {0.0f, 0.0f};
-        iterate<float, DM>(h, dd, io.cap, exc, fixed, wilk, st, io.iters, n, i, [&](int k, cx<float> v) {
+        iterate<float, DM, AHEAD>(h, dd, io.cap, exc, fixed, wilk, st, io.iters, n, i, [&](int k, cx<float> v) {
             // k is a compile-time constant after inlining
 #pragma unroll
             for (int q = 0; q < DM; ++q)
@@ -992,11 +1120,11 @@ __global__ __launch_bounds__(kBlock) void solve_pair_kernel(PolyIO io)
 // occupancy, which spills.
 // One lane per polynomial in index order (all polynomials of one degree, or
 // no degree array).
-template <bool FP32, int DM, int BIN>
+template <bool FP32, int DM, int BIN, bool AHEAD>
 __global__ __launch_bounds__(kBlock) void solve_flat_kernel(PolyIO io)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    solve_poly<FP32, DM, BIN>(io, i, i < io.n);
+    solve_poly<FP32, DM, BIN, AHEAD>(io, i, i < io.n);
 }
 
 // Mixed degrees, one persistent launch.  Each block is one wave and walks
@@ -1085,7 +1213,7 @@ __global__ __launch_bounds__(kWave) void solve_tiled_kernel(PolyIO io, int tile)
 // one XCD (b = xcd + 8 q) take the slots of one tile in turn: a tile's
 // slices run together on one XCD and share its L2, which holds the tile's
 // coefficients for all of them.
-template <bool FP32, int DM, int BIN>
+template <bool FP32, int DM, int BIN, bool AHEAD>
 __global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile, int slots,
                                                              int64_t ntiles)
 {
@@ -1145,7 +1273,25 @@ __global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile
     __syncthreads();
     const uint16_t e = list[lane];
     const bool valid = e != 0xFFFF;
-    solve_poly<FP32, DM, BIN>(io, base + (valid ? e : 0), valid);
+    solve_poly<FP32, DM, BIN, AHEAD>(io, base + (valid ? e : 0), valid);
+}
+
+template <bool FP32, int DM, int BIN, bool AHEAD>
+hipError_t launch_one_per_lane(const PolyIO& io, const SolveArgs& a, hipStream_t stream)
+{
+    if (a.degrees && a.tile > 0) {
+        const int tile = a.tile;
+        const int64_t tiles = (a.n + tile - 1) / tile;
+        const int slots = (tile + kWave - 1) / kWave + DM;  // >= the slices of any tile
+        const int64_t sliced = (tiles + 7) / 8 * 8 * slots;
+        hipLaunchKernelGGL((solve_sliced_kernel<FP32, DM, BIN, AHEAD>), dim3((unsigned)sliced),
+                           dim3(kWave), 0, stream, io, tile, slots, tiles);
+    } else {
+        const int64_t blocks = (a.n + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((solve_flat_kernel<FP32, DM, BIN, AHEAD>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, stream, io);
+    }
+    return hipGetLastError();
 }
 
 template <bool FP32, int DM, int BIN>
@@ -1157,8 +1303,9 @@ hipError_t launch_layout(const PolyIO& io, const SolveArgs& a, hipStream_t strea
         const int slots = (tile + kWave - 1) / kWave + DM;  // >= the slices of any tile
         const int64_t sliced = (tiles + 7) / 8 * 8 * slots;
         if (a.grid_blocks == 0 && sliced <= 0x7fffffff) {
-            hipLaunchKernelGGL((solve_sliced_kernel<FP32, DM, BIN>), dim3((unsigned)sliced),
-                               dim3(kWave), 0, stream, io, tile, slots, tiles);
+            if (a.flags & PR_FLAG_RUN_AHEAD)
+                return launch_one_per_lane<FP32, DM, BIN, true>(io, a, stream);
+            return launch_one_per_lane<FP32, DM, BIN, false>(io, a, stream);
         } else {
             const int64_t want = a.grid_blocks > 0 ? a.grid_blocks : a.fallback_grid;
             const int64_t grid = want < tiles ? want : tiles;
@@ -1169,10 +1316,10 @@ hipError_t launch_layout(const PolyIO& io, const SolveArgs& a, hipStream_t strea
         const int64_t blocks = (a.n + 2 * kBlock - 1) / (2 * kBlock);
         hipLaunchKernelGGL((solve_pair_kernel<DM, BIN == kBinReread ? kBinNone : BIN>),
                            dim3((unsigned)blocks), dim3(kBlock), 0, stream, io);
+    } else if (a.flags & PR_FLAG_RUN_AHEAD) {
+        return launch_one_per_lane<FP32, DM, BIN, true>(io, a, stream);
     } else {
-        const int64_t blocks = (a.n + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL((solve_flat_kernel<FP32, DM, BIN>), dim3((unsigned)blocks),
-                           dim3(kBlock), 0, stream, io);
+        return launch_one_per_lane<FP32, DM, BIN, false>(io, a, stream);
     }
     return hipGetLastError();
 }

@@ -56,7 +56,8 @@ inline int check_solve_opts(const pr_solve_opts* opts, int max_tile, pr_solve_op
         return PR_ERR_INVALID_ARG;
     if (o.flags &
         ~(uint32_t)(PR_FLAG_NO_EXCEPTIONAL_SHIFT | PR_FLAG_FIXED_STEPS | PR_FLAG_FP64_FALLBACK |
-                    PR_FLAG_RAYLEIGH_SHIFT | PR_FLAG_PAIRED_LANES))
+                    PR_FLAG_RAYLEIGH_SHIFT | PR_FLAG_PAIRED_LANES |
+                    PR_FLAG_RUN_AHEAD))
         return PR_ERR_UNSUPPORTED;
     if (o.tile < -1 || o.tile > max_tile || o.grid_blocks < 0)
         return PR_ERR_INVALID_ARG;

@@ -66,7 +66,7 @@ def test_build_records_kernel_instruction_digests(lib):
     import json
     from paper_2507_02164_amd import build as b
     d = json.load(open(b.ISA_DIGESTS))
-    timed = "_ZN6proots12_GLOBAL__N_117solve_flat_kernelILb1ELi6ELi2EEEvNS0_6PolyIOE"
+    timed = "_ZN6proots12_GLOBAL__N_117solve_flat_kernelILb1ELi6ELi2ELb0EEEvNS0_6PolyIOE"
     assert timed in d and len(d[timed]) == 64
     asm = "_Zk:\n  v_add_f32 v0, v1, v2 ; c\n.LBB0_1:\n  .p2align 2\n  s_endpgm\n"
     asm2 = "_Zk: ; other comment\n  v_add_f32 v0, v1, v2\n.LBB9_9:\n  s_endpgm ; end\n"
@@ -103,10 +103,10 @@ def test_solve_argument_validation(lib):
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_INVALID_ARG
     bad = pr.SolveOpts(flags=0x80)
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
-    bad = pr.SolveOpts(flags=0x20)
+    bad = pr.SolveOpts(flags=0x40)
     assert lib.pr_solve(fake, None, 10, 6, fake, fake, ctypes.byref(bad), None) == pr.PR_ERR_UNSUPPORTED
     fb = pr.SolveOpts(precision=pr.FP32_POLISH, flags=pr.FLAG_FP64_FALLBACK | pr.FLAG_FIXED_STEPS |
-                      pr.FLAG_RAYLEIGH_SHIFT)
+                      pr.FLAG_RAYLEIGH_SHIFT | pr.FLAG_PAIRED_LANES | pr.FLAG_RUN_AHEAD)
     assert lib.pr_solve(fake, None, 0, 6, fake, fake, ctypes.byref(fb), None) == pr.PR_OK
     # more polynomials than one launch's grid can cover
     assert lib.pr_solve(fake, None, 0x7fffffff * 64 + 1, 6, fake, fake, None, None) == pr.PR_ERR_INVALID_ARG
