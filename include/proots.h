@@ -95,7 +95,9 @@ enum pr_solve_flags {
                                                on the same stream that reads the status array
                                                and solves only those); its roots, status (with
                                                PR_ST_RESOLVED_FP64) and iteration counts are
-                                               then the FP64 solve's.  No effect on PR_FP64 */
+                                               then the FP64 solve's in lock-step levels
+                                               (PR_FLAG_RUN_AHEAD does not apply to this
+                                               launch).  No effect on PR_FP64 */
     PR_FLAG_PAIRED_LANES = 1u << 4,         /* FP32 form, index-order launch (no tiles):
                                                each lane solves two polynomials, 64 apart,
                                                stepping both matrices in one level loop;

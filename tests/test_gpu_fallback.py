@@ -50,7 +50,10 @@ def test_fallback_replaces_exactly_the_flagged(name):
     dd = None if deg is None else to_dev(deg)
     kw = dict(max_iter_per_level=30)
     r0, s0 = pr.solve(ad, dd, "fp32_polish", **kw)
-    r64, s64, it64 = pr.solve(ad, dd, "fp64", iter_counts=True, **kw)
+    # the fallback's second launch steps its lanes in lock-step, as the
+    # index-order FP64 launch does (any run-ahead the tuner picks for the
+    # first launch does not carry over)
+    r64, s64, it64 = pr.solve(ad, dd, "fp64", iter_counts=True, tile=-1, grid_blocks=0, **kw)
     rf, sf, itf = pr.solve(ad, dd, "fp32_polish", flags=pr.FLAG_FP64_FALLBACK, iter_counts=True,
                            **kw)
     torch.cuda.synchronize()
@@ -65,6 +68,28 @@ def test_fallback_replaces_exactly_the_flagged(name):
     assert np.array_equal(to_host(itf)[:, flagged], to_host(it64)[:, flagged])
     # what is left flagged after the fallback is what FP64 itself flags
     assert ((sf & FB) != 0).sum() == ((s64[flagged] & FB) != 0).sum()
+
+
+@pytest.mark.parametrize("name", ["clustered", "mixed"])
+def test_fallback_after_a_run_ahead_launch(name):
+    """The first launch with lanes running ahead, the fallback in lock-step:
+    unflagged results are the run-ahead launch's, flagged ones the
+    lock-step FP64 solve's, bit for bit."""
+    a, deg, _, _ = _case(name)
+    ad = to_dev(np.ascontiguousarray(a))
+    dd = None if deg is None else to_dev(deg)
+    lay = dict(max_iter_per_level=30, tile=-1 if deg is None else 512, grid_blocks=0)
+    r0, s0 = pr.solve(ad, dd, "fp32_polish", flags=pr.FLAG_RUN_AHEAD, **lay)
+    r64, s64 = pr.solve(ad, dd, "fp64", max_iter_per_level=30, tile=-1, grid_blocks=0)
+    rf, sf = pr.solve(ad, dd, "fp32_polish", flags=pr.FLAG_RUN_AHEAD | pr.FLAG_FP64_FALLBACK, **lay)
+    torch.cuda.synchronize()
+    s0, s64, sf = (to_host(x).astype(np.uint32) for x in (s0, s64, sf))
+    flagged = (s0 & FB) != 0
+    assert flagged.any()
+    b0, b64, bf = _bits(r0), _bits(r64), _bits(rf)
+    assert np.array_equal(bf[:, ~flagged], b0[:, ~flagged])
+    assert np.array_equal(bf[:, flagged], b64[:, flagged])
+    assert np.array_equal(sf[flagged], s64[flagged] | pr.ST_RESOLVED_FP64)
 
 
 @pytest.mark.parametrize("store", [True, False])
