@@ -1351,10 +1351,20 @@ hipError_t launch_dm(const SolveArgs& a, hipStream_t stream)
     const bool fallback = FP32 && (a.flags & PR_FLAG_FP64_FALLBACK);
     io.defer_mask = fallback ? kFallbackBits : 0;
     hipError_t e;
-    if (!a.win.hist)
+    if (!a.win.hist) {
         e = launch_layout<FP32, DM, kBinNone>(io, a, stream);
-    else
+    } else if constexpr (!FP32) {
+        // FP64 with lanes running ahead and the roots stored: the pixels are
+        // taken from the stored roots at the end instead of being kept in
+        // registers through the level loops (168 VGPRs instead of 174, so 3
+        // waves per SIMD instead of 2)
+        if (a.roots && (a.flags & PR_FLAG_RUN_AHEAD))
+            e = launch_layout<FP32, DM, kBinReread>(io, a, stream);
+        else
+            e = launch_layout<FP32, DM, kBinKeep>(io, a, stream);
+    } else {
         e = launch_layout<FP32, DM, kBinKeep>(io, a, stream);
+    }
     if (e != hipSuccess || !fallback)
         return e;
     // FP64 fallback: a second launch over the polynomials the first one

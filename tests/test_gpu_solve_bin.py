@@ -79,6 +79,22 @@ def test_fused_equals_solve_then_density(name, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
+@pytest.mark.parametrize("name", ["gaussian", "clustered", "mixed"])
+def test_fused_with_run_ahead(name, precision):
+    """Lanes running ahead, in the index-order layout (and for mixed degrees
+    also in the sliced one): the same contract.  FP64 with the roots stored
+    takes the pixels from the stored roots at the end; without them it keeps
+    them in registers."""
+    a, deg, win, shape = _case(name)
+    skip = SKIP_ALL if name == "clustered" else 0
+    _compare(a, deg, win, shape, precision, skip, tile=-1, grid_blocks=0,
+             flags=pr.FLAG_RUN_AHEAD)
+    if deg is not None:
+        _compare(a, deg, win, shape, precision, skip, tile=512, grid_blocks=0,
+                 flags=pr.FLAG_RUN_AHEAD)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_polish"])
 def test_fused_mixed_flat_layout_and_fixed_steps(precision):
     a, deg, win, shape = _case("mixed")
     _compare(a, deg, win, shape, precision, 0, tile=-1)
