@@ -47,13 +47,6 @@ __device__ __forceinline__ double cabs1_d(cx<T> a)
 __device__ __forceinline__ float abs_t(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double abs_t(double x) { return __builtin_fabs(x); }
 
-// |Re z| + |Im z| in the storage precision.
-template <typename T>
-__device__ __forceinline__ T cabs1_t(cx<T> a)
-{
-    return abs_t(a.re) + abs_t(a.im);
-}
-
 template <typename T>
 __device__ __forceinline__ bool finite(cx<T> a) { return isfinite(a.re) && isfinite(a.im); }
 

@@ -371,12 +371,10 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int d
                                      Emit&& emit)
 {
     const bool here = m == M;
-    // the test in the sweeps' precision (its sums round at the 2^-24 level
-    // in FP32, far inside any margin the threshold itself has)
-    const T hh = cabs1_t(h[M - 1][M - 2]);
-    const T tt = cabs1_t(h[M - 1][M - 1]) + cabs1_t(h[M - 2][M - 2]);
+    const double hh = cabs1_d(h[M - 1][M - 2]);
+    const double tt = cabs1_d(h[M - 1][M - 1]) + cabs1_d(h[M - 2][M - 2]);
     // fixed-step mode (Alg. 2): no test, exactly `cap` steps per level
-    const bool conv = !fixed && hh <= T(Eps<T>::v) * tt;
+    const bool conv = !fixed && hh <= Eps<T>::v * tt;
     const bool done = here && (conv || its == cap);
     if (done) {
         if (!conv && !fixed)
@@ -418,9 +416,8 @@ __device__ __forceinline__ void trip(cx<T> (&h)[DM][DM], int& m, int& its, int d
     // the exceptional shift (10th and 20th step of a level), computed in
     // FP64 only when some lane of the wave takes it
     if (__ballot(ex && act)) {  // wave-uniform
-        const double hx = cabs1_d(h[M - 1][M - 2]);
-        const T ere = (T)((double)h[M - 1][M - 1].re + hx * 0.75);
-        const T eim = (T)((double)h[M - 1][M - 1].im + hx * 0.5);
+        const T ere = (T)((double)h[M - 1][M - 1].re + hh * 0.75);
+        const T eim = (T)((double)h[M - 1][M - 1].im + hh * 0.5);
         mu = {pick(ex, ere, mu.re), pick(ex, eim, mu.im)};
     }
     const cx<T> sh = {pick(act, mu.re, T(0)), pick(act, mu.im, T(0))};
@@ -446,12 +443,10 @@ __device__ __forceinline__ void trip_ahead(cx<T> (&h)[DM][DM], int& m, int& its,
     static_assert(M >= 4, "run-ahead trips are taken from level 4 up");
     constexpr int L = M - 1;
     const bool here = m == M;
-    // the test in the sweeps' precision (its sums round at the 2^-24 level
-    // in FP32, far inside any margin the threshold itself has)
-    const T hh = cabs1_t(h[M - 1][M - 2]);
-    const T tt = cabs1_t(h[M - 1][M - 1]) + cabs1_t(h[M - 2][M - 2]);
+    const double hh = cabs1_d(h[M - 1][M - 2]);
+    const double tt = cabs1_d(h[M - 1][M - 1]) + cabs1_d(h[M - 2][M - 2]);
     // fixed-step mode (Alg. 2): no test, exactly `cap` steps per level
-    const bool conv = !fixed && hh <= T(Eps<T>::v) * tt;
+    const bool conv = !fixed && hh <= Eps<T>::v * tt;
     const bool done = here && (conv || its == cap);
     if (done) {
         if (!conv && !fixed)
@@ -463,9 +458,9 @@ __device__ __forceinline__ void trip_ahead(cx<T> (&h)[DM][DM], int& m, int& its,
     // the lanes at level L and their test there (itb: their steps at L)
     const bool below = m == L || done;
     const int itb = done ? 0 : its;
-    const T hhb = cabs1_t(h[L - 1][L - 2]);
-    const T ttb = cabs1_t(h[L - 1][L - 1]) + cabs1_t(h[L - 2][L - 2]);
-    const bool convb = !fixed && hhb <= T(Eps<T>::v) * ttb;
+    const double hhb = cabs1_d(h[L - 1][L - 2]);
+    const double ttb = cabs1_d(h[L - 1][L - 1]) + cabs1_d(h[L - 2][L - 2]);
+    const bool convb = !fixed && hhb <= Eps<T>::v * ttb;
     const bool done_b = below && (convb || itb == cap);
     if (done_b) {
         if (!convb && !fixed)
@@ -515,7 +510,7 @@ __device__ __forceinline__ void trip_ahead(cx<T> (&h)[DM][DM], int& m, int& its,
     }
     // the exceptional shift (10th and 20th step of a level)
     if (__ballot(ex && stp)) {  // wave-uniform
-        const double hx = act_b ? cabs1_d(h[L - 1][L - 2]) : cabs1_d(h[M - 1][M - 2]);
+        const double hx = act_b ? hhb : hh;
         const T ere = (T)((double)e.re + hx * 0.75);
         const T eim = (T)((double)e.im + hx * 0.5);
         mu = {pick(ex, ere, mu.re), pick(ex, eim, mu.im)};
