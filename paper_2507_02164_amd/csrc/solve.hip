@@ -185,8 +185,9 @@ __device__ __forceinline__ void rot_cols_zero_real(cx<T>& x, cx<T>& y, cx<T> c, 
 // executed by every lane of the wave.  Lanes with act == false take the
 // identity rotation (c, s) = (1, 0) and shift 0 throughout, which leaves
 // the values of their matrix unchanged (1*x + 0*y == x for finite y; a zero
-// may change sign); the entries a real rotation overwrites are selected.  Running the step wave-uniformly, with no
-// lane-divergent branch around it, matters: a divergent branch would keep
+// may change sign); the entries a real rotation overwrites are selected.
+// Running the step wave-uniformly, with no lane-divergent branch around it,
+// matters: a divergent branch would keep
 // the pre-step matrix of the lanes that skip it alive next to the post-step
 // matrix of the lanes that take it, doubling the register footprint.
 //

@@ -383,6 +383,21 @@ def test_run_ahead_matches_the_oracle(precision, source, rule):
     assert same > (0.98 if precision == "fp64" else 0.9)
 
 
+@pytest.mark.parametrize("dmax", [4, 5])
+def test_run_ahead_smaller_dmax(dmax):
+    """Batches whose dmax is below 6: run-ahead trips from level 4 up only."""
+    rng = np.random.default_rng(90 + dmax)
+    n = 20000
+    b = (rng.standard_normal((dmax + 1, n)) + 1j * rng.standard_normal((dmax + 1, n))) / np.sqrt(2)
+    deg = rng.integers(2, dmax + 1, n).astype(np.int32)
+    ref, ref_st = oracle.solve(b, deg, flags=OW)
+    for precision in ("fp64", "fp32_polish"):
+        for tile in (-1, 256):
+            got, st = _solve(b, deg, precision, tile=tile, grid_blocks=0, flags=pr.FLAG_RUN_AHEAD)
+            assert np.array_equal(st & 0x7, ref_st & 0x7)
+            _check_roots(got, st, b, deg, ref, ref_st, floor=1e-9, flagged_ok=precision != "fp64")
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4097])
 def test_run_ahead_ragged_degrees_and_fixed_steps(n):
     """Run-ahead on ragged batches with every degree 0..dmax+1 (invalid
