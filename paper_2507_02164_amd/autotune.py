@@ -1,7 +1,8 @@
 """Launch-layout autotuner for pr_solve.
 
 For a sample of the caller's workload it times every candidate layout on
-the GPU (HIP events, median of repeats) and keeps the fastest:
+the GPU (HIP events, the best over two passes of the median of repeats,
+after a second of warm-up launches) and keeps the fastest:
 
   * tile         -- polynomials per degree-sorted tile (mixed degrees only),
   * grid_blocks  -- the mixed-degree launch's shape: 0 for one wave per (tile,
@@ -46,6 +47,8 @@ SLICED_TILES = (128, 256, 512, 1024, 2048)
 CAPS = (20, 24, 30)
 DEFAULT_CAP = 30
 CAP_MARGIN = 0.03
+WARMUP_S = 1.0
+ROUNDS = 2
 
 _cache = None
 
@@ -102,7 +105,7 @@ def _time(fn, reps):
     return ts[len(ts) // 2]
 
 
-def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> dict:
+def tune(coeffs, degrees=None, precision="fp32_polish", reps=5, log=print) -> dict:
     """Time the candidate layouts on this sample; returns the record
     {"options": {...}, "ms": best, "trials": [...]}."""
     dmax = coeffs.shape[0] - 1
@@ -116,6 +119,12 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
         flags = (_capi.FLAG_PAIRED_LANES if paired else 0) | (_capi.FLAG_RUN_AHEAD if ahead else 0)
         _capi.solve(coeffs, degrees, precision, roots=roots, status=status, flags=flags, **o)
 
+    # warm the GPU up first (clocks ramp over the first launches; without
+    # this the first trials time slower than the same layout later)
+    t_end = time.perf_counter() + WARMUP_S
+    while time.perf_counter() < t_end:
+        run(max_iter_per_level=30, tile=-1)
+        torch.cuda.synchronize()
     # caps that flag nothing extra
     run(max_iter_per_level=30, tile=-1)
     torch.cuda.synchronize()
@@ -132,13 +141,19 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=3, log=print) -> di
     if degrees is not None:
         layouts += [dict(tile=t, grid_blocks=0, ahead=a) for t in SLICED_TILES for a in (0, 1)]
         layouts += [dict(tile=t, grid_blocks=b * cus) for t in TILES for b in BLOCKS_PER_CU]
-    trials = []
-    for cap in caps:
-        for lay in layouts:
-            o = dict(lay, max_iter_per_level=cap)
+    # every candidate is timed in ROUNDS passes over the whole list, the
+    # later passes in reverse order, and keeps its best median: a drift of
+    # the GPU's clock over the run then favours no position in the list
+    cands = [dict(lay, max_iter_per_level=cap) for cap in caps for lay in layouts]
+    best_ms = [float("inf")] * len(cands)
+    for rnd in range(ROUNDS):
+        order = range(len(cands)) if rnd % 2 == 0 else reversed(range(len(cands)))
+        for k in order:
+            o = cands[k]
             ms = _time(lambda: run(**o), reps)
-            trials.append({"options": o, "ms": ms})
+            best_ms[k] = min(best_ms[k], ms)
             log(f"  {precision} {o}: {ms:.3f} ms")
+    trials = [{"options": o, "ms": ms} for o, ms in zip(cands, best_ms)]
     best = min(trials, key=lambda t: t["ms"])
     at_default = [t for t in trials if t["options"]["max_iter_per_level"] == DEFAULT_CAP]
     if at_default:
