@@ -769,7 +769,7 @@ struct PolyIO {
 constexpr uint32_t kFallbackBits = PR_ST_NOT_CONVERGED | PR_ST_POLISH_UNCONVERGED;
 
 // Solve polynomial i on this lane.  valid == false: the lane has no
-// polynomial this round and only rides along in the wave's level loops.
+// polynomial to solve and only rides along in the wave's level loops.
 // FP32 selects the FP32-sweep + FP64-polish form; BIN != kBinNone adds the
 // binning epilogue (kBinKeep lets io.roots be null).  No early return: every
 // lane of the wave reaches the wave-uniform loops and the epilogue's ballots.
