@@ -505,7 +505,8 @@ def test_roots_far_from_unit_scale(precision, exps):
     accuracy with that imbalance (1.8e-11 at 2^9, no digits at 2^60)."""
     for e in exps:
         a, roots = _scaled_lattice(e, seed=e & 0xFF)
-        got, st = _solve(a, None, precision)
-        assert np.all(st == 0), (e, np.unique(st))
-        err = rel_err(match(got, roots), roots)
-        assert err.max() < 1e-12, (e, err.max())
+        for flags in (0, pr.FLAG_RUN_AHEAD):
+            got, st = _solve(a, None, precision, flags=flags)
+            assert np.all(st == 0), (e, flags, np.unique(st))
+            err = rel_err(match(got, roots), roots)
+            assert err.max() < 1e-12, (e, flags, err.max())
