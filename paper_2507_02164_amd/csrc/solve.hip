@@ -644,15 +644,19 @@ __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs
 {
     uint32_t st = 0;
     cx<double> lead = {0.0, 0.0};
+    // Every row is read and the rows above the degree are ignored: loads
+    // that no lane condition guards are all in flight before the first is
+    // used (a load per row under its own condition waited for each one).
+    double2 v[DM + 1];
+#pragma unroll
+    for (int k = 0; k <= DM; ++k)
+        v[k] = coeffs[(int64_t)k * n + i];
 #pragma unroll
     for (int k = 0; k <= DM; ++k) {
-        a[k] = {0.0, 0.0};
-        if (k <= d) {
-            double2 v = coeffs[(int64_t)k * n + i];
-            a[k] = {v.x, v.y};
-            if (!finite(a[k]))
-                st |= PR_ST_NONFINITE;
-        }
+        const bool in = k <= d;
+        a[k] = {in ? v[k].x : 0.0, in ? v[k].y : 0.0};
+        if (in && !finite(a[k]))
+            st |= PR_ST_NONFINITE;
         if (k == d)
             lead = a[k];
     }
@@ -871,16 +875,18 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
             // may still be in L2 here.  The roots are stored nontemporally
             // below for the same reason: as ordinary stores they would evict
             // coefficients that other waves are about to read again.
+            // (every row read, as in load_poly, so that the loads overlap)
+            double2 v[DM + 1];
+#pragma unroll
+            for (int k = 0; k <= DM; ++k)
+                v[k] = load_stream(io.coeffs_again + (int64_t)k * n + i);
 #pragma unroll
             for (int k = 0; k <= DM; ++k) {
-                a[k] = {0.0, 0.0};
-                if (k <= d) {
-                    // a_k 2^(s (k - d)): the coefficients of 2^(-s d) p(2^s w),
-                    // so that the polish below runs in the sweeps' variable w
-                    const double2 v = load_stream(io.coeffs_again + (int64_t)k * n + i);
-                    const int e = sc * (k - d);
-                    a[k] = {__builtin_ldexp(v.x, e), __builtin_ldexp(v.y, e)};
-                }
+                // a_k 2^(s (k - d)): the coefficients of 2^(-s d) p(2^s w),
+                // so that the polish below runs in the sweeps' variable w
+                const bool in = k <= d;
+                const int e = sc * (k - d);
+                a[k] = {in ? __builtin_ldexp(v[k].x, e) : 0.0, in ? __builtin_ldexp(v[k].y, e) : 0.0};
             }
             cx<double> r[DM];
             double last2[DM];
@@ -1140,6 +1146,7 @@ __global__ __launch_bounds__(kBlock) void solve_flat_kernel(PolyIO io)
 // more than reading the status array.
 constexpr int kTileMax = 4096;
 constexpr int kWave = 64;
+constexpr int kBatch = 8;  // chunks of 64 degrees read together by the sliced kernel
 
 template <bool FP32, int DM, int BIN, bool SELECT>
 __global__ __launch_bounds__(kWave) void solve_tiled_kernel(PolyIO io, int tile)
@@ -1227,22 +1234,42 @@ __global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile
     const int64_t base = t * tile;
     const int cnt_t = (int)((io.n - base) < tile ? (io.n - base) : tile);
     const int lane = threadIdx.x;
-    auto bucket = [&](int64_t g) -> int {
-        const int d = io.degrees[g];
-        return (d >= 1 && d <= DM) ? d : 0;
+    auto degree_bucket = [](int d) -> int { return (d >= 1 && d <= DM) ? d : 0; };
+    // buckets of tile entries t0 + u*64 + lane, u < kBatch (-1 past the
+    // tile).  A whole batch inside the tile takes its loads unconditionally,
+    // so that they are all in flight before the first is used; only the
+    // tile's last, partial batch loads lane by lane.
+    auto load_buckets = [&](int t0, int (&bk)[kBatch]) {
+        if (t0 + kBatch * kWave <= cnt_t) {  // wave-uniform
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u)
+                bk[u] = degree_bucket(io.degrees[base + t0 + u * kWave + lane]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int tt = t0 + u * kWave + lane;
+                bk[u] = tt < cnt_t ? degree_bucket(io.degrees[base + tt]) : -1;
+            }
+        }
     };
     // bucket sizes (bucket 0 = invalid degree), then the slot's bucket and
-    // the rank within it of the slice's first polynomial
+    // the rank within it of the slice's first polynomial.  The tile's
+    // degrees are read kBatch chunks of 64 at a time, every load of a batch
+    // issued before the first is used: one memory round trip per batch
+    // instead of one per chunk (a chunk-by-chunk loop kept the waves of this
+    // kernel waiting on memory for about 40% of their cycles).
     int count[DM + 1];
 #pragma unroll
     for (int k = 0; k <= DM; ++k)
         count[k] = 0;
-    for (int t0 = 0; t0 < cnt_t; t0 += kWave) {
-        const int tt = t0 + lane;
-        const int bk = tt < cnt_t ? bucket(base + tt) : -1;
+    for (int t0 = 0; t0 < cnt_t; t0 += kBatch * kWave) {
+        int bk[kBatch];
+        load_buckets(t0, bk);
 #pragma unroll
-        for (int k = 0; k <= DM; ++k)
-            count[k] += __builtin_popcountll(__ballot(bk == k));
+        for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+            for (int k = 0; k <= DM; ++k)
+                count[k] += __builtin_popcountll(__ballot(bk[u] == k));
     }
     int mine = -1, r0 = 0, acc = 0;
 #pragma unroll
@@ -1262,14 +1289,18 @@ __global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this lane
     int rank = 0;
-    for (int t0 = 0; t0 < cnt_t && rank < r0 + kWave; t0 += kWave) {
-        const int tt = t0 + lane;
-        const int bk = tt < cnt_t ? bucket(base + tt) : -1;
-        const uint64_t m = __ballot(bk == mine);
-        const int r = rank + __builtin_popcountll(m & below);
-        if (bk == mine && r >= r0 && r < r0 + kWave)
-            list[r - r0] = (uint16_t)tt;
-        rank += __builtin_popcountll(m);
+    for (int t0 = 0; t0 < cnt_t && rank < r0 + kWave; t0 += kBatch * kWave) {
+        int bk[kBatch];
+        load_buckets(t0, bk);
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int tt = t0 + u * kWave + lane;
+            const uint64_t m = __ballot(bk[u] == mine);
+            const int r = rank + __builtin_popcountll(m & below);
+            if (bk[u] == mine && r >= r0 && r < r0 + kWave)
+                list[r - r0] = (uint16_t)tt;
+            rank += __builtin_popcountll(m);
+        }
     }
     __syncthreads();
     const uint16_t e = list[lane];
