@@ -1,8 +1,8 @@
 """Launch-layout autotuner for pr_solve.
 
 For a sample of the caller's workload it times every candidate layout on
-the GPU (HIP events, the best over two passes of the median of repeats,
-after a second of warm-up launches) and keeps the fastest:
+the GPU (HIP events, the best over three passes of the median of repeats,
+after three seconds of warm-up launches) and keeps the fastest:
 
   * tile         -- polynomials per degree-sorted tile (mixed degrees only),
   * grid_blocks  -- the mixed-degree launch's shape: 0 for one wave per (tile,
@@ -43,12 +43,12 @@ DEFAULT_CACHE = os.path.join(_HERE, "tuning", "tune_cache.json")
 
 TILES = (512, 1024, 2048, 4096)
 BLOCKS_PER_CU = (8, 16, 32, 64, 128)
-SLICED_TILES = (128, 256, 512, 1024, 2048)
+SLICED_TILES = (128, 256, 512, 1024, 2048, 4096)
 CAPS = (20, 24, 30)
 DEFAULT_CAP = 30
 CAP_MARGIN = 0.03
-WARMUP_S = 1.0
-ROUNDS = 2
+WARMUP_S = 3.0
+ROUNDS = 3
 
 _cache = None
 
@@ -141,9 +141,11 @@ def tune(coeffs, degrees=None, precision="fp32_polish", reps=5, log=print) -> di
     if degrees is not None:
         layouts += [dict(tile=t, grid_blocks=0, ahead=a) for t in SLICED_TILES for a in (0, 1)]
         layouts += [dict(tile=t, grid_blocks=b * cus) for t in TILES for b in BLOCKS_PER_CU]
-    # every candidate is timed in ROUNDS passes over the whole list, the
-    # later passes in reverse order, and keeps its best median: a drift of
-    # the GPU's clock over the run then favours no position in the list
+    # every candidate is timed in ROUNDS passes over the whole list, every
+    # other pass in reverse order, and keeps its best median: a drift of the
+    # GPU's clock over the run then favours no position in the list (warm-up
+    # alone does not settle it: after three seconds of it the first pass's
+    # first trials still timed up to 20% slower than the same layouts later)
     cands = [dict(lay, max_iter_per_level=cap) for cap in caps for lay in layouts]
     best_ms = [float("inf")] * len(cands)
     for rnd in range(ROUNDS):

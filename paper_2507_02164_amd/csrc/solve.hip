@@ -1211,24 +1211,33 @@ __global__ __launch_bounds__(kWave) void solve_tiled_kernel(PolyIO io, int tile)
 }
 
 // Mixed degrees, one block (one wave) per (tile, slice): no loop around the
-// solve, so the kernel keeps the flat kernel's register allocation (FP32 96
-// VGPRs, 5 waves per SIMD; FP64 160-166, 3 waves) where the persistent tile
+// solve, so the kernel keeps the flat kernel's register allocation (FP32 94
+// VGPRs, 5 waves per SIMD; FP64 156-168, 3 waves) where the persistent tile
 // loop above costs 10-20 more (one wave per SIMD fewer).  Block b takes slot
-// `slot` of tile t: the tile's polynomials are bucketed by degree as above
-// (index order within a bucket, each bucket cut into slices of 64), and slot
-// s is the s-th slice in bucket order; a slot past the tile's slices exits at
-// once.  Blocks are dealt to the 8 XCDs round-robin, so consecutive blocks of
-// one XCD (b = xcd + 8 q) take the slots of one tile in turn: a tile's
-// slices run together on one XCD and share its L2, which holds the tile's
-// coefficients for all of them.
+// `slot` of tile t: the tile's polynomials are sorted by degree, highest
+// first (index order within a degree), and slot s takes sorted positions
+// 64 s .. 64 s + 63; a slot past the tile's end exits at once.  So every
+// slice but the tile's last is full, and only the slices at a degree
+// boundary mix degrees.  Blocks are dealt to the 8 XCDs round-robin, so
+// consecutive blocks of one XCD (b = xcd + 8 q) take the slots of one tile in
+// turn: a tile's slices run together on one XCD and share its L2, which holds
+// the tile's coefficients for all of them.
 template <bool FP32, int DM, int BIN, bool AHEAD>
 __global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile, int slots,
                                                              int64_t ntiles)
 {
     const int64_t b = blockIdx.x;
     const int64_t q = b >> 3;
-    const int slot = (int)(q % slots);
-    const int64_t t = (q / slots) * 8 + (b & 7);
+    const int64_t g = q / slots;  // tile group: tiles 8 g .. 8 g + 7, one per XCD
+    // Each group takes its slots in an order rotated by g.  With the same
+    // order in every group, slot s (whose cost follows its degree) fell on
+    // the same position modulo 8 or 16 of every XCD's block sequence at tiles
+    // of 512 or 1024, and the wave counters showed about 30% fewer resident
+    // waves and up to 11% more time: in-order workgroup dispatch over a
+    // fixed cycle of shader engines would give one engine all the costly
+    // slices.  Rotated, the same work ran 8-12% faster at those tiles.
+    const int slot = (int)((q + g) % slots);
+    const int64_t t = g * 8 + (b & 7);
     if (t >= ntiles)
         return;
     const int64_t base = t * tile;
@@ -1252,12 +1261,11 @@ __global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile
             }
         }
     };
-    // bucket sizes (bucket 0 = invalid degree), then the slot's bucket and
-    // the rank within it of the slice's first polynomial.  The tile's
-    // degrees are read kBatch chunks of 64 at a time, every load of a batch
-    // issued before the first is used: one memory round trip per batch
-    // instead of one per chunk (a chunk-by-chunk loop kept the waves of this
-    // kernel waiting on memory for about 40% of their cycles).
+    // bucket sizes (bucket 0 = invalid degree).  The tile's degrees are read
+    // kBatch chunks of 64 at a time, every load of a batch issued before the
+    // first is used: one memory round trip per batch instead of one per
+    // chunk (a chunk-by-chunk loop kept the waves of this kernel waiting on
+    // memory for about 40% of their cycles).
     int count[DM + 1];
 #pragma unroll
     for (int k = 0; k <= DM; ++k)
@@ -1271,36 +1279,49 @@ __global__ __launch_bounds__(kWave) void solve_sliced_kernel(PolyIO io, int tile
             for (int k = 0; k <= DM; ++k)
                 count[k] += __builtin_popcountll(__ballot(bk[u] == k));
     }
-    int mine = -1, r0 = 0, acc = 0;
-#pragma unroll
-    for (int k = 0; k <= DM; ++k) {
-        const int slices = (count[k] + kWave - 1) / kWave;
-        if (mine < 0 && slot < acc + slices) {
-            mine = k;
-            r0 = (slot - acc) * kWave;
-        }
-        acc += slices;
-    }
-    if (mine < 0)
+    // The tile in sorted order: degree DM first, down to degree 1, then the
+    // invalid degrees, each bucket in index order.  The slot takes sorted
+    // positions p0 .. p0 + 63.  Only the tile's last slice is partly empty; a
+    // slice at a bucket boundary holds two (or, for buckets of fewer than 64,
+    // more) degrees, whose lower-degree lanes wait for their level (or, with
+    // run-ahead, step one level below inside the higher level's trips).
+    const int p0 = slot * kWave;
+    if (p0 >= cnt_t)
         return;
-    // the slice's tile-local indices, in index order
+    // the slice's tile-local indices, in sorted order
     __shared__ uint16_t list[kWave];
     list[lane] = 0xFFFF;
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this lane
-    int rank = 0;
-    for (int t0 = 0; t0 < cnt_t && rank < r0 + kWave; t0 += kBatch * kWave) {
-        int bk[kBatch];
-        load_buckets(t0, bk);
+    int start = 0;  // sorted position of bucket k's first member
+#pragma unroll 1
+    for (int k = DM; k >= 0; --k) {
+        int ck = 0;  // count[k], by selects (no dynamic index into registers)
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int tt = t0 + u * kWave + lane;
-            const uint64_t m = __ballot(bk[u] == mine);
-            const int r = rank + __builtin_popcountll(m & below);
-            if (bk[u] == mine && r >= r0 && r < r0 + kWave)
-                list[r - r0] = (uint16_t)tt;
-            rank += __builtin_popcountll(m);
+        for (int j = 0; j <= DM; ++j)
+            ck = j == k ? count[j] : ck;
+        // ranks r0 .. r1 - 1 of bucket k fall in the slice
+        const int r0 = p0 - start > 0 ? p0 - start : 0;
+        const int r1 = p0 + kWave - start < ck ? p0 + kWave - start : ck;
+        if (r0 < r1) {  // wave-uniform
+            int rank = 0;
+            for (int t0 = 0; t0 < cnt_t && rank < r1; t0 += kBatch * kWave) {
+                int bk[kBatch];
+                load_buckets(t0, bk);
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int tt = t0 + u * kWave + lane;
+                    const uint64_t m = __ballot(bk[u] == k);
+                    const int r = rank + __builtin_popcountll(m & below);
+                    if (bk[u] == k && r >= r0 && r < r1)
+                        list[start + r - p0] = (uint16_t)tt;
+                    rank += __builtin_popcountll(m);
+                }
+            }
         }
+        start += ck;
+        if (start >= p0 + kWave)
+            break;
     }
     __syncthreads();
     const uint16_t e = list[lane];
@@ -1314,7 +1335,7 @@ hipError_t launch_one_per_lane(const PolyIO& io, const SolveArgs& a, hipStream_t
     if (a.degrees && a.tile > 0) {
         const int tile = a.tile;
         const int64_t tiles = (a.n + tile - 1) / tile;
-        const int slots = (tile + kWave - 1) / kWave + DM;  // >= the slices of any tile
+        const int slots = (tile + kWave - 1) / kWave;  // the slices of a full tile
         const int64_t sliced = (tiles + 7) / 8 * 8 * slots;
         hipLaunchKernelGGL((solve_sliced_kernel<FP32, DM, BIN, AHEAD>), dim3((unsigned)sliced),
                            dim3(kWave), 0, stream, io, tile, slots, tiles);
@@ -1332,7 +1353,7 @@ hipError_t launch_layout(const PolyIO& io, const SolveArgs& a, hipStream_t strea
     if (a.degrees && a.tile > 0) {
         const int tile = a.tile;
         const int64_t tiles = (a.n + tile - 1) / tile;
-        const int slots = (tile + kWave - 1) / kWave + DM;  // >= the slices of any tile
+        const int slots = (tile + kWave - 1) / kWave;  // the slices of a full tile
         const int64_t sliced = (tiles + 7) / 8 * 8 * slots;
         if (a.grid_blocks == 0 && sliced <= 0x7fffffff) {
             if (a.flags & PR_FLAG_RUN_AHEAD)
