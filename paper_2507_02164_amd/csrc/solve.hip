@@ -644,13 +644,18 @@ __device__ __forceinline__ uint32_t load_poly(const double2* __restrict__ coeffs
 {
     uint32_t st = 0;
     cx<double> lead = {0.0, 0.0};
-    // Every row is read and the rows above the degree are ignored: loads
-    // that no lane condition guards are all in flight before the first is
-    // used (a load per row under its own condition waited for each one).
+    // Each row that some lane of the wave needs is read by every lane, and
+    // the rows above a lane's degree are ignored: the loads sit under
+    // wave-uniform conditions only, so they are all in flight before the
+    // first is used (a load per row under its own lane condition waited for
+    // each one), and rows above every lane's degree are not read at all.
     double2 v[DM + 1];
 #pragma unroll
-    for (int k = 0; k <= DM; ++k)
-        v[k] = coeffs[(int64_t)k * n + i];
+    for (int k = 0; k <= DM; ++k) {
+        v[k] = make_double2(0.0, 0.0);
+        if (__ballot(k <= d))
+            v[k] = coeffs[(int64_t)k * n + i];
+    }
 #pragma unroll
     for (int k = 0; k <= DM; ++k) {
         const bool in = k <= d;
@@ -875,11 +880,14 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
             // may still be in L2 here.  The roots are stored nontemporally
             // below for the same reason: as ordinary stores they would evict
             // coefficients that other waves are about to read again.
-            // (every row read, as in load_poly, so that the loads overlap)
+            // (rows read as in load_poly, so that the loads overlap)
             double2 v[DM + 1];
 #pragma unroll
-            for (int k = 0; k <= DM; ++k)
-                v[k] = load_stream(io.coeffs_again + (int64_t)k * n + i);
+            for (int k = 0; k <= DM; ++k) {
+                v[k] = make_double2(0.0, 0.0);
+                if (__ballot(k <= d))
+                    v[k] = load_stream(io.coeffs_again + (int64_t)k * n + i);
+            }
 #pragma unroll
             for (int k = 0; k <= DM; ++k) {
                 // a_k 2^(s (k - d)): the coefficients of 2^(-s d) p(2^s w),
