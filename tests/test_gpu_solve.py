@@ -401,15 +401,17 @@ def test_run_ahead_smaller_dmax(dmax):
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4097])
 def test_run_ahead_ragged_degrees_and_fixed_steps(n):
     """Run-ahead on ragged batches with every degree 0..dmax+1 (invalid
-    ones flagged, rows beyond the degree NaN), in both layouts and forms, and
-    in fixed-step mode (exactly T steps per level, as without it)."""
+    ones flagged, rows beyond the degree NaN), in index order and in
+    degree-sorted tiles (of 128, and of 100: slices that straddle several
+    degrees and a partial last slice per tile), in both forms, and in
+    fixed-step mode (exactly T steps per level, as without it)."""
     rng = np.random.default_rng(70 + n)
     b = (rng.standard_normal((7, n)) + 1j * rng.standard_normal((7, n))) / np.sqrt(2)
     deg = rng.integers(0, 8, n).astype(np.int32)
     deg[0] = 6
     ref, ref_st = oracle.solve(b, deg, flags=OW)
     for precision in ("fp64", "fp32_polish"):
-        for tile in (-1, 128):
+        for tile in (-1, 128, 100):
             got, st = _solve(b, deg, precision, tile=tile, grid_blocks=0, flags=pr.FLAG_RUN_AHEAD)
             assert np.array_equal(st & 0x7, ref_st & 0x7)
             _check_roots(got, st, b, deg, ref, ref_st, floor=1e-9, flagged_ok=precision != "fp64")
