@@ -144,20 +144,25 @@ typedef struct pr_solve_opts {
     int32_t* iter_counts;         /* optional DEVICE array [dmax-1][n] (row m-2 = QR steps
                                      taken at level m), or NULL */
     int32_t tile;                 /* with a degrees array: polynomials are solved in tiles of
-                                     this many consecutive indices, each sorted by degree so
-                                     that every wave holds one degree (one persistent launch);
+                                     this many consecutive indices, each sorted by degree
+                                     (highest first) before it is cut into waves of 64, so
+                                     that nearly every wave holds one degree (one launch);
                                      0 = library default (2048), -1 = no sorting (index order);
                                      valid -1..4096 */
-    int32_t grid_blocks;          /* tiled launch: 0 = one one-wave block per (tile, slice of
-                                     64 same-degree polynomials); > 0 = that many persistent
-                                     one-wave blocks walking the tiles; valid >= 0 */
+    int32_t grid_blocks;          /* tiled launch: 0 = one one-wave block per 64 consecutive
+                                     polynomials of a sorted tile (only a slice at a degree
+                                     boundary mixes degrees); > 0 = that many persistent
+                                     one-wave blocks walking the tiles, each degree of a tile
+                                     cut into its own slices; valid >= 0 */
 } pr_solve_opts;
 
 /*
  * pr_solve -- roots of n polynomials.
  *
  *   coeffs   [dmax+1][n] pr_complex, row k = a_k of p_i(z) = sum_k a_k z^k.
- *            Rows above a polynomial's degree are not read.  Any nonzero
+ *            Rows above a polynomial's degree are ignored (they may hold
+ *            anything, NaN included; a wave may read them for another lane
+ *            whose degree is higher, but never uses them).  Any nonzero
  *            leading coefficient a_d is accepted (the polynomial is divided
  *            by it first, Sec. II-B).
  *   degrees  [n] int32 degree of each polynomial, or NULL (= all dmax).

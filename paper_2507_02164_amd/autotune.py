@@ -5,10 +5,10 @@ the GPU (HIP events, the best over three passes of the median of repeats,
 after three seconds of warm-up launches) and keeps the fastest:
 
   * tile         -- polynomials per degree-sorted tile (mixed degrees only),
-  * grid_blocks  -- the mixed-degree launch's shape: 0 for one wave per (tile,
-                    slice of 64 same-degree polynomials), or the number of
-                    persistent one-wave blocks walking the tiles (tried at
-                    several per compute unit),
+  * grid_blocks  -- the mixed-degree launch's shape: 0 for one wave per 64
+                    consecutive polynomials of a degree-sorted tile, or the
+                    number of persistent one-wave blocks walking the tiles
+                    (tried at several per compute unit),
   * paired       -- FP32 form, index order: one or two polynomials per lane
                     (PR_FLAG_PAIRED_LANES),
   * ahead        -- one-per-lane launches: lock-step levels, or lanes one

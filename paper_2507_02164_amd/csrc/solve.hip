@@ -45,10 +45,11 @@
 //   * FP32 form: sweeps in FP32, test in FP64, then every root is polished
 //     by Newton steps r <- r - p(r)/p'(r) in FP64 on the original
 //     coefficients.
-//   * Mixed degrees: polynomials are bucketed by degree within tiles of
-//     consecutive indices, so that each wave holds one degree; either one
-//     wave per (tile, slice) (solve_sliced_kernel, the default) or persistent
-//     waves walking the tiles (solve_tiled_kernel).
+//   * Mixed degrees: polynomials are sorted by degree within tiles of
+//     consecutive indices, so that nearly every wave holds one degree;
+//     either one wave per 64 consecutive polynomials of a sorted tile
+//     (solve_sliced_kernel, the default) or persistent waves walking the
+//     tiles, each degree cut into its own slices (solve_tiled_kernel).
 //   * Binning epilogue (Sec. III's roots-to-pixels path, optional): once
 //     the status is final, the wave counts every lane's roots with merged
 //     atomics -- the same decisions and counts as the density kernel over
