@@ -757,7 +757,8 @@ constexpr int kBinKeep = 2;    // pixel indices kept in registers (roots optiona
 // Everything a lane needs to solve one polynomial.
 struct PolyIO {
     const double2* coeffs;
-    const double2* coeffs_again;  // same array, second pointer: the FP32 form re-reads it
+    const double2* coeffs_again;  // same array, second pointer: the polish of the paired-lane
+                                  // and persistent-tile launches re-reads it
     const int32_t* degrees;
     int64_t n;
     double2* roots;
@@ -778,12 +779,28 @@ struct PolyIO {
 // Status bits that send an FP32 result to the FP64 fallback.
 constexpr uint32_t kFallbackBits = PR_ST_NOT_CONVERGED | PR_ST_POLISH_UNCONVERGED;
 
+// The FP32 form's copy of its wave's original coefficients, row k of lane l
+// at [k][l], written when they are first read and read back by the polish:
+// 7 KiB per one-wave block, so the 5 waves per SIMD that the registers allow
+// still fit the CU's 160 KiB of LDS.  Reading them again from memory instead
+// fetched about twice their bytes where a wave's polynomials are scattered
+// over a degree-sorted tile (each 128-byte line is shared with the waves of
+// other degrees, which finish at other times).
+template <int DM>
+__device__ __forceinline__ double2 (*coeff_stash())[kBlock]
+{
+    __shared__ double2 stash[DM + 1][kBlock];
+    return stash;
+}
+
 // Solve polynomial i on this lane.  valid == false: the lane has no
 // polynomial to solve and only rides along in the wave's level loops.
 // FP32 selects the FP32-sweep + FP64-polish form; BIN != kBinNone adds the
-// binning epilogue (kBinKeep lets io.roots be null).  No early return: every
-// lane of the wave reaches the wave-uniform loops and the epilogue's ballots.
-template <bool FP32, int DM, int BIN, bool AHEAD = false>
+// binning epilogue (kBinKeep lets io.roots be null).  STASH (FP32 form,
+// one-wave blocks): the polish takes the coefficients from coeff_stash
+// rather than from memory.  No early return: every lane of the wave reaches
+// the wave-uniform loops and the epilogue's ballots.
+template <bool FP32, int DM, int BIN, bool AHEAD = false, bool STASH = true>
 __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool valid)
 {
     using T = typename std::conditional<FP32, float, double>::type;
@@ -804,6 +821,12 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
         a[k] = b[k] = {0.0, 0.0};
     if (valid && !st)
         st = load_poly<DM>(io.coeffs, n, i, d, a, b);
+    if constexpr (FP32 && STASH) {
+        // a holds the rows up to the degree and zeros above it
+#pragma unroll
+        for (int k = 0; k <= DM; ++k)
+            coeff_stash<DM>()[k][threadIdx.x] = make_double2(a[k].re, a[k].im);
+    }
     const bool ok = valid && !st;
     const int dd = ok ? d : 0;  // 0: this lane takes no level
     if (valid) {
@@ -874,20 +897,24 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
         });
         e[0] = h[0][0];
         if (ok) {
-            // The original coefficients, read again (through a second
-            // pointer, so the compiler cannot keep the first load alive
-            // across the QR loop).  This is their last use, so the read is
-            // nontemporal; the first read is an ordinary one so that they
-            // may still be in L2 here.  The roots are stored nontemporally
-            // below for the same reason: as ordinary stores they would evict
-            // coefficients that other waves are about to read again.
-            // (rows read as in load_poly, so that the loads overlap)
+            // The original coefficients again: from the LDS copy, or
+            // (!STASH) read again through a second pointer, so that the
+            // compiler cannot keep the first load alive across the QR loop.
+            // That read is their last use, so it is nontemporal; the first
+            // read is an ordinary one so that they may still be in L2 here.
+            // The roots are stored nontemporally below: as ordinary stores
+            // they would evict coefficients that other waves are about to
+            // read.  (Rows read as in load_poly, so that the loads overlap.)
             double2 v[DM + 1];
 #pragma unroll
             for (int k = 0; k <= DM; ++k) {
-                v[k] = make_double2(0.0, 0.0);
-                if (__ballot(k <= d))
-                    v[k] = load_stream(io.coeffs_again + (int64_t)k * n + i);
+                if constexpr (STASH) {
+                    v[k] = coeff_stash<DM>()[k][threadIdx.x];
+                } else {
+                    v[k] = make_double2(0.0, 0.0);
+                    if (__ballot(k <= d))
+                        v[k] = load_stream(io.coeffs_again + (int64_t)k * n + i);
+                }
             }
 #pragma unroll
             for (int k = 0; k <= DM; ++k) {
@@ -1155,6 +1182,7 @@ __global__ __launch_bounds__(kBlock) void solve_flat_kernel(PolyIO io)
 // more than reading the status array.
 constexpr int kTileMax = 4096;
 constexpr int kWave = 64;
+static_assert(kWave == kBlock, "solve_poly's LDS copy of the coefficients is indexed by threadIdx.x");
 constexpr int kBatch = 8;  // chunks of 64 degrees read together by the sliced kernel
 
 template <bool FP32, int DM, int BIN, bool SELECT>
@@ -1213,7 +1241,7 @@ __global__ __launch_bounds__(kWave) void solve_tiled_kernel(PolyIO io, int tile)
         for (int s = 0; s < total; s += kWave) {
             const uint16_t e = list[s + lane];
             const bool valid = e != 0xFFFF;
-            solve_poly<FP32, DM, BIN>(io, base + (valid ? e : 0), valid);
+            solve_poly<FP32, DM, BIN, false, false>(io, base + (valid ? e : 0), valid);
         }
         __syncthreads();
     }
