@@ -59,4 +59,25 @@ __device__ __forceinline__ void wave_count(int b, int32_t* __restrict__ hist, in
         atomicAdd(hist + b, 1);
 }
 
+// Add 1 at pixel b (b < 0: nothing) for every lane of the wave, merging
+// runs of consecutive lanes that hold the same pixel; all lanes must call it
+// together.  A lane starts a run where its pixel differs from the previous
+// lane's (lane 0 always); the run ends before the next such lane, and its
+// first lane adds the run's length with one atomic.  Every lane with b >= 0
+// lies in exactly one run that starts at or before it with the same pixel,
+// so each is counted once.  Where lanes hold consecutive polynomials of a
+// smooth family, a root moves through its pixels in runs, which this merges
+// at a fixed cost of a few instructions; distinct pixels cost one atomic
+// each, as plain atomics would.
+__device__ __forceinline__ void run_count(int b, int32_t* __restrict__ hist)
+{
+    const int lane = __lane_id();
+    const int prev = __shfl_up(b, 1);
+    const uint64_t starts = __ballot(lane == 0 || b != prev);
+    const uint64_t after = lane == 63 ? 0ull : starts >> (lane + 1);
+    const int len = after ? __builtin_ctzll(after) + 1 : 64 - lane;
+    if (b >= 0 && (lane == 0 || b != prev))
+        atomicAdd(hist + b, len);
+}
+
 }  // namespace proots

@@ -11,8 +11,8 @@
 //
 // One lane per polynomial.  All of a lane's root rows are loaded first
 // (coalesced 16-byte-per-lane reads, all in flight together), then binned
-// row by row with the wave merging equal pixels before its atomics
-// (`wave_count`).
+// row by row, each run of consecutive lanes on one pixel with one atomic
+// (`run_count`).
 //
 // Local form (the front-end's roots, in each disk's variable w): a root
 // counts only when |w|^2 < rmax2, at z = c + rho w (each part a rounded
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
     }
 #pragma unroll
     for (int k = 0; k < DM; ++k)
-        wave_count(bin[k], win.hist);
+        run_count(bin[k], win.hist);
 }
 
 template <int DM>
