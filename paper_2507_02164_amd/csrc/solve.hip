@@ -974,7 +974,7 @@ __device__ __forceinline__ void solve_poly(const PolyIO& io, int64_t i, bool val
         const bool keep = valid && !(st & (io.skip_mask | io.defer_mask));
 #pragma unroll
         for (int k = 0; k < DM; ++k)
-            wave_count(keep ? bins[k] : -1, io.win.hist);
+            run_count(keep ? bins[k] : -1, io.win.hist);
     }
 }
 
