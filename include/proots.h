@@ -224,7 +224,8 @@ int pr_density(const pr_complex* roots, const int32_t* degrees, const uint32_t* 
  * updated once, by one thread.  This pays off
  * when the roots of neighbouring polynomials fall on different pixels (e.g.
  * random coefficients); for smooth families whose neighbours share pixels
- * pr_density's wave-merged atomics are as fast.
+ * pr_density, which adds each run of neighbours on one pixel with one
+ * atomic, is faster.
  *
  *   workspace        DEVICE memory owned by the caller, 256-byte aligned,
  *                    of at least pr_density_sorted_workspace(n, dmax, width,

@@ -33,32 +33,6 @@ __device__ __forceinline__ int pixel_of(double re, double im, const BinWindow& w
     return -1;
 }
 
-// Add 1 at pixel b (b < 0: nothing) for every lane of the wave; all lanes
-// must call it together.  Neighbouring polynomials of a smooth family put
-// their roots into the same few pixels, and many lanes adding to one
-// address serialise in the memory system, so equal pixels are merged first:
-// the lowest pending lane's pixel is broadcast, every lane holding it is
-// counted with one ballot, and one lane adds the count.  After `rounds`
-// merges the remaining lanes add 1 each, so a wave of distinct pixels costs
-// little more than plain atomics.
-__device__ __forceinline__ void wave_count(int b, int32_t* __restrict__ hist, int rounds = 8)
-{
-    const int lane = __lane_id();
-    uint64_t pending = __ballot(b >= 0);
-    for (int round = 0; round < rounds && pending; ++round) {
-        const int leader = __builtin_ctzll(pending);
-        const int lb = __builtin_amdgcn_readlane(b, leader);
-        const uint64_t same = __ballot(b == lb);
-        if (lane == leader)
-            atomicAdd(hist + lb, __builtin_popcountll(same));
-        if (b == lb)
-            b = -1;
-        pending &= ~same;
-    }
-    if (b >= 0)
-        atomicAdd(hist + b, 1);
-}
-
 // Add 1 at pixel b (b < 0: nothing) for every lane of the wave, merging
 // runs of consecutive lanes that hold the same pixel; all lanes must call it
 // together.  A lane starts a run where its pixel differs from the previous

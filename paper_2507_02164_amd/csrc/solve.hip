@@ -1144,7 +1144,7 @@ __device__ __forceinline__ void solve_pair(const PolyIO& io, const int64_t (&i)[
             const bool keep = valid[p] && !(st[p] & (io.skip_mask | io.defer_mask));
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                wave_count(keep ? bins[k] : -1, io.win.hist);
+                run_count(keep ? bins[k] : -1, io.win.hist);
         }
     }
 }
