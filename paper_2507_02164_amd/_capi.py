@@ -161,7 +161,7 @@ def _prepare_solve(coeffs, degrees, precision, max_iter_per_level, polish_steps,
     if max_iter_per_level is None or tile is None or grid_blocks is None:
         from . import autotune
         name = {v: k for k, v in PRECISIONS.items()}.get(prec, str(prec))
-        tuned = autotune.tuned_options(name, dmax, degrees is not None, dev)
+        tuned = autotune.tuned_options(name, dmax, degrees is not None, dev, n)
         if max_iter_per_level is None:
             max_iter_per_level = tuned.get("max_iter_per_level", 0)
         # the tuned layout (tile, and its flags) only when the caller left

@@ -22,11 +22,15 @@ after three seconds of warm-up launches) and keeps the fastest:
                     alone would otherwise pick it half of the time).
 
 Results go to a JSON cache keyed by architecture, form, dmax and degree mix
-(``PROOTS_TUNE_CACHE`` overrides the path).  ``tuned_options`` reads it;
-``paper_2507_02164_amd.solve`` consults it when the caller leaves the layout
-options unset.
+(``PROOTS_TUNE_CACHE`` overrides the path); uniform batches small enough to
+leave the GPU latency-bound (at most ``SMALL_WAVES_PER_SIMD`` one-wave blocks
+per SIMD) have keys of their own, tuned on a sample of that size, since
+their best layout differs from a large batch's.  ``tuned_options`` reads the
+cache; ``paper_2507_02164_amd.solve`` consults it when the caller leaves the
+layout options unset.
 
-    python -m paper_2507_02164_amd.autotune     # tunes the standard workloads
+    python -m paper_2507_02164_amd.autotune [uniform|uniform_small|mixed ...]
+                                                # tunes the standard workloads
 """
 from __future__ import annotations
 
@@ -49,6 +53,9 @@ DEFAULT_CAP = 30
 CAP_MARGIN = 0.03
 WARMUP_S = 3.0
 ROUNDS = 3
+# a uniform batch of at most this many one-wave blocks per SIMD (64
+# polynomials each, 4 SIMDs per compute unit) is looked up under its own key
+SMALL_WAVES_PER_SIMD = 2
 
 _cache = None
 
@@ -58,6 +65,7 @@ def cache_path() -> str:
 
 
 _arch = {}
+_cus = {}
 
 
 def arch_name(device=None) -> str:
@@ -69,8 +77,25 @@ def arch_name(device=None) -> str:
     return _arch[idx]
 
 
-def key(arch, precision, dmax, mixed) -> str:
-    return f"{arch}/{precision}/dmax{dmax}/{'mixed' if mixed else 'uniform'}"
+def key(arch, precision, dmax, mixed, small=False) -> str:
+    kind = "mixed" if mixed else ("uniform_small" if small else "uniform")
+    return f"{arch}/{precision}/dmax{dmax}/{kind}"
+
+
+def small_limit(compute_units) -> int:
+    """Largest uniform batch looked up under the small-batch key."""
+    return compute_units * 4 * 64 * SMALL_WAVES_PER_SIMD
+
+
+def lookup(cache, arch, precision, dmax, mixed, n=None, compute_units=None) -> dict:
+    """Options for a batch of n polynomials from a cache dict: a small
+    uniform batch takes its own key when that was tuned, every other batch
+    (and a small one without it) the key of its form, dmax and degree mix."""
+    if not mixed and n is not None and compute_units and n <= small_limit(compute_units):
+        rec = cache.get(key(arch, precision, dmax, False, small=True))
+        if rec is not None:
+            return dict(rec.get("options", {}))
+    return dict(cache.get(key(arch, precision, dmax, mixed), {}).get("options", {}))
 
 
 def load_cache() -> dict:
@@ -81,12 +106,16 @@ def load_cache() -> dict:
     return _cache
 
 
-def tuned_options(precision, dmax, mixed, device=None) -> dict:
-    """Options recorded for this configuration ({} when none were tuned)."""
+def tuned_options(precision, dmax, mixed, device=None, n=None) -> dict:
+    """Options recorded for this configuration and batch size ({} when none
+    were tuned)."""
     if not torch.cuda.is_available():
         return {}
-    c = load_cache()
-    return dict(c.get(key(arch_name(device), precision, dmax, mixed), {}).get("options", {}))
+    idx = torch.device(device).index if device is not None else 0
+    idx = 0 if idx is None else idx
+    if idx not in _cus:
+        _cus[idx] = torch.cuda.get_device_properties(idx).multi_processor_count
+    return lookup(load_cache(), arch_name(device), precision, dmax, mixed, n, _cus[idx])
 
 
 def _time(fn, reps):
@@ -185,18 +214,25 @@ def main():
     import workloads
     dev = torch.device("cuda:0")
     arch = arch_name(dev)
+    # (mixed, small): sample
     samples = {
-        False: (torch.from_numpy(workloads.parametric(2048, seed=0)).to(dev), None),
+        (False, False): (torch.from_numpy(workloads.parametric(2048, seed=0)).to(dev), None),
+        # one wave per SIMD: the 65,536-polynomial Gaussian batch
+        (False, True): (torch.from_numpy(workloads.gaussian(65536, seed=0)).to(dev), None),
     }
     # the persistent grid's best size depends on the batch (work per block):
     # the mixed-degree layouts are tuned at the size of the 64 Mi workload
     a, d = workloads.mixed(64 * 2 ** 20, seed=0)
-    samples[True] = (torch.from_numpy(a).to(dev), torch.from_numpy(d).to(dev))
-    for mixed, (c, deg) in samples.items():
+    samples[(True, False)] = (torch.from_numpy(a).to(dev), torch.from_numpy(d).to(dev))
+    only = set(sys.argv[1:])  # optional: tune only these kinds (uniform, uniform_small, mixed)
+    for (mixed, small), (c, deg) in samples.items():
+        kind = key("", "", 0, mixed, small).rsplit("/", 1)[1]
+        if only and kind not in only:
+            continue
         for precision in ("fp32_polish", "fp64"):
-            print(f"tuning {precision} {'mixed' if mixed else 'uniform'} on n={c.shape[1]}", flush=True)
+            print(f"tuning {precision} {kind} on n={c.shape[1]}", flush=True)
             rec = tune(c, deg, precision)
-            save(key(arch, precision, c.shape[0] - 1, mixed), rec)
+            save(key(arch, precision, c.shape[0] - 1, mixed, small), rec)
             print(f"  -> {rec['options']} {rec['ms']:.3f} ms", flush=True)
 
 

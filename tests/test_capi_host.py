@@ -213,6 +213,28 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     assert autotune.load_cache()[k]["options"]["tile"] == 1024
 
 
+def test_autotune_small_batch_lookup():
+    """A small uniform batch takes its own key when tuned, else the uniform
+    one; mixed batches and larger ones never take it (no GPU: dict lookups)."""
+    from paper_2507_02164_amd import autotune
+    big = autotune.key("gfx950", "fp64", 6, False)
+    small = autotune.key("gfx950", "fp64", 6, False, small=True)
+    mixed = autotune.key("gfx950", "fp64", 6, True)
+    assert small == "gfx950/fp64/dmax6/uniform_small" and big == "gfx950/fp64/dmax6/uniform"
+    cache = {big: {"options": {"tile": -1}}, small: {"options": {"tile": -1, "ahead": 1}},
+             mixed: {"options": {"tile": 1024, "ahead": 1}}}
+    lim = autotune.small_limit(256)
+    assert lim == 256 * 4 * 64 * autotune.SMALL_WAVES_PER_SIMD
+    look = lambda mx, n, c=cache: autotune.lookup(c, "gfx950", "fp64", 6, mx, n, 256)
+    assert look(False, 65536) == {"tile": -1, "ahead": 1}
+    assert look(False, lim) == {"tile": -1, "ahead": 1}
+    assert look(False, lim + 1) == {"tile": -1}
+    assert look(False, None) == {"tile": -1}
+    assert look(True, 1000) == {"tile": 1024, "ahead": 1}
+    assert look(False, 1000, {big: cache[big]}) == {"tile": -1}   # small key not tuned
+    assert look(False, 1000, {}) == {}
+
+
 def test_committed_tuning_cache_is_valid():
     import json
     from paper_2507_02164_amd import autotune
