@@ -698,11 +698,18 @@ template <int DM, int K0, int G>
 __device__ __forceinline__ void polish_group(cx<double> (&r)[DM], const cx<double> (&a)[DM + 1],
                                              int steps, double (&last2)[DM])
 {
+    // the last step's correction and whether it could be taken; last2 is
+    // formed from them once, after the loop (0 when no step was asked for)
+    cx<double> delta[G], p[G];
+    bool step[G];
 #pragma unroll
-    for (int g = K0; g < K0 + G; ++g)
-        last2[g] = 0.0;
+    for (int g = 0; g < G; ++g) {
+        delta[g] = {0.0, 0.0};
+        p[g] = {0.0, 0.0};
+        step[g] = true;
+    }
     for (int s = 0; s < steps; ++s) {
-        cx<double> p[G], dp[G];
+        cx<double> dp[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             p[g] = a[DM];
@@ -718,20 +725,23 @@ __device__ __forceinline__ void polish_group(cx<double> (&r)[DM], const cx<doubl
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const double den = norm2(dp[g]);
-            cx<double> delta = {0.0, 0.0};
-            const bool step = den >= 0x1p-1022 && isfinite(den);
-            if (step) {
+            delta[g] = {0.0, 0.0};
+            step[g] = den >= 0x1p-1022 && isfinite(den);
+            if (step[g]) {
                 const cx<double> q = p[g] * conj(dp[g]);
                 const double y0 = __builtin_amdgcn_rcp(den);
                 const double inv = __builtin_fma(y0, __builtin_fma(-den, y0, 1.0), y0);
-                delta = {q.re * inv, q.im * inv};
+                delta[g] = {q.re * inv, q.im * inv};
             }
-            r[K0 + g] = r[K0 + g] - delta;
-            // a step that cannot be taken counts as converged only at an
-            // exact root
-            const bool at_root = p[g].re == 0.0 && p[g].im == 0.0;
-            last2[K0 + g] = step ? norm2(delta) : (at_root ? 0.0 : __builtin_inf());
+            r[K0 + g] = r[K0 + g] - delta[g];
         }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        // a step that cannot be taken counts as converged only at an exact
+        // root
+        const bool at_root = p[g].re == 0.0 && p[g].im == 0.0;
+        last2[K0 + g] = step[g] ? norm2(delta[g]) : (at_root ? 0.0 : __builtin_inf());
     }
 }
 
